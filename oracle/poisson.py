@@ -1,0 +1,114 @@
+"""Curvilinear Poisson solve, eqs. (6)-(7), second-order finite differences, FP64.
+
+Oracle module (test infrastructure only; the product path never imports it).
+
+Paper passages: Section 2, eq. (6) (Poisson's equation in (x1, x2)), eq. (7)
+(the Laplace operator, including the mixed d2/dx1dx2 term and the first-order
+d/dx2 term), the statement that finite-difference derivatives on the uniform
+grid are second order and that the linear system is solved by LU decomposition,
+and Section 1 (both boundaries held at fixed potentials).
+
+Readings (the paper does not spell these out):
+  * normalised units: lengths in R0, potential in Te/e, density in n0, so eq. (6)
+    reads  Lap(phi) = -(R0/lambda_D)^2 * sum_s q_s n_s  (q_s in units of e);
+  * Dirichlet rows at the grain x1 = -1 (phi_grain) and at x1 = x1_out (phi_out);
+  * interior nodes use the 9-point central stencil: second differences for
+    d2/dx1^2 and d2/dx2^2, the four-corner central formula for d2/dx1dx2, central
+    first difference for d/dx2;
+  * on the symmetry axis (x2 = +-1) the coefficients of d2/dx2^2 and d2/dx1dx2
+    vanish (they carry 1 - x2^2), so the row keeps the d2/dx1^2 term and the
+    d/dx2 term, the latter by the second-order one-sided difference
+    (+-3 phi_j -+ 4 phi_{j-+1} +- phi_{j-+2}) / (2 h2).
+The linear system is factorised by sparse LU (SuperLU through scipy), the
+library routine standing in for the LAPACK LU the paper names, and each solve is
+followed by two steps of FP64 iterative refinement (as LAPACK's expert drivers
+do): the operator's rows differ in scale by ~r^4, and without refinement the
+LU round-off alone reaches ~1e-9 of |phi| on a 512 x 512 grid.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import geometry as geo
+
+
+def assemble(grid):
+    """Sparse matrix of the discrete operator over all nodes (Dirichlet rows are
+    identity rows).  Unknown ordering: node (i1, i2) -> i2 (N1 + 1) + i1."""
+    n1, n2 = grid.n1, grid.n2
+    h1, h2 = grid.h1, grid.h2
+    nx = n1 + 1
+    X1, X2 = grid.mesh()
+    c11, c22, c12, c2 = geo.laplace_coeffs(X1, X2, grid.alpha)
+    rows, cols, vals = [], [], []
+
+    def put(j, i, jj, ii, v):
+        rows.append(j * nx + i)
+        cols.append(jj * nx + ii)
+        vals.append(v)
+
+    for j in range(n2 + 1):
+        for i in range(n1 + 1):
+            if i == 0 or i == n1:
+                put(j, i, j, i, 1.0)
+                continue
+            a11 = c11[j, i] / (h1 * h1)
+            put(j, i, j, i - 1, a11)
+            put(j, i, j, i + 1, a11)
+            put(j, i, j, i, -2.0 * a11)
+            if j == 0 or j == n2:
+                # one-sided d/dx2 at the axis; d2/dx2^2 and mixed terms vanish
+                b = c2[j, i] / (2.0 * h2)
+                sgn = 1 if j == 0 else -1          # direction into the domain
+                # forward (j=0):  (-3 p0 + 4 p1 - p2) / (2 h2)
+                # backward (j=N): ( 3 pN - 4 pN-1 + pN-2) / (2 h2)
+                put(j, i, j, i, -3.0 * sgn * b)
+                put(j, i, j + sgn, i, 4.0 * sgn * b)
+                put(j, i, j + 2 * sgn, i, -1.0 * sgn * b)
+                continue
+            a22 = c22[j, i] / (h2 * h2)
+            b2 = c2[j, i] / (2.0 * h2)
+            a12 = c12[j, i] / (4.0 * h1 * h2)
+            put(j, i, j - 1, i, a22 - b2)
+            put(j, i, j + 1, i, a22 + b2)
+            put(j, i, j, i, -2.0 * a22)
+            put(j, i, j + 1, i + 1, a12)
+            put(j, i, j - 1, i - 1, a12)
+            put(j, i, j + 1, i - 1, -a12)
+            put(j, i, j - 1, i + 1, -a12)
+    nn = (n1 + 1) * (n2 + 1)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nn, nn))
+
+
+class PoissonSolver:
+    """Factorises the operator once; solve() maps a right-hand side to phi."""
+
+    def __init__(self, grid):
+        self.grid = grid
+        self.A = assemble(grid)
+        self.lu = spla.splu(self.A.tocsc())
+
+    def rhs(self, source, phi_grain, phi_out):
+        """Right-hand side: `source` (values of Lap(phi) at the nodes, [i2, i1])
+        on the unknown nodes, boundary potentials on the Dirichlet rows."""
+        b = np.array(source, dtype=np.float64, copy=True)
+        b[:, 0] = phi_grain
+        b[:, -1] = phi_out
+        return b
+
+    def solve(self, source, phi_grain, phi_out):
+        return self.solve_rhs(self.rhs(source, phi_grain, phi_out))
+
+    def solve_rhs(self, b, refine=2):
+        """Solve with a full right-hand side already holding the boundary rows."""
+        b = np.asarray(b, dtype=np.float64).ravel()
+        x = self.lu.solve(b)
+        for _ in range(refine):
+            x = x + self.lu.solve(b - self.A @ x)
+        return x.reshape(self.grid.shape)
+
+
+def source_from_density(charge_density, lambdaD_over_R0):
+    """eq. (6) in normalised units: Lap(phi) = -(R0/lambda_D)^2 * rho,
+    rho = sum_s q_s n_s (units of e n0)."""
+    return -np.asarray(charge_density, dtype=np.float64) / (lambdaD_over_R0 ** 2)
