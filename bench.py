@@ -1,0 +1,152 @@
+"""Benchmark of the aspherical PIC particle loop on one MI355X.
+
+A step is one full PIC step of the library (particle push with gather, boundary
+tests and deposit for both species; Maxwellian injection; periodic cell sort;
+charge density, FP64 multigrid Poisson solve and nodal gradient; grain force).
+`value` is particle-steps per second over the timed steps (resident particles of
+both species pushed per step, summed, divided by the wall time between two
+device synchronisations), inputs resident in HBM before timing starts.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+[--workload c3] [--no-fp64] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_PARTICLE = {"fp32": 48, "fp64": 80}   # read + write of the particle state
+
+
+def run_gpu(w, precision, steps, warmup, stream):
+    import torch
+    import paper_2307_11107_amd as apic
+    sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]),
+          apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])]
+    cfg = apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"],
+                         kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"])
+    prec = apic.APIC_FP32_SPLIT if precision == "fp32" else apic.APIC_FP64
+    ctx = apic.apic_init([cfg], apic.opts(precision=prec, inject=True, stream=stream))
+    try:
+        for s in range(2):
+            apic.apic_inject(ctx, 0, s)
+        apic.apic_step(ctx, warmup)
+        torch.cuda.synchronize()
+        t0 = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        apic.apic_set_profiling(ctx, True)
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        apic.apic_step(ctx, steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - start
+        tm = apic.apic_timing(ctx)
+        t1 = apic.apic_tallies(ctx, 0, 2, w["n2"])
+    finally:
+        apic.apic_free(ctx)
+    pushed = int(sum(t1["particle_steps"]) - sum(t0["particle_steps"]))
+    return {"elapsed": elapsed, "particle_steps": pushed, "timing": tm,
+            "resident": [int(x) for x in t1["resident"]],
+            "balance_exact": all(int(t1["injected"][s]) == int(t1["absorbed"][s] + t1["escaped"][s] + t1["resident"][s])
+                                 for s in range(2))}
+
+
+def cpu_baseline(w, n_sample, steps):
+    """The FP64 oracle on a bounded sample of the workload (same geometry, field
+    solve and step; fewer macro-particles)."""
+    from oracle.pic import Config, Simulation, Species
+    cfg = Config(alpha=w["alpha"], n1=w["n1"], n2=w["n2"], x1_out=w["x1_out"], wce=w["wce"],
+                 kappa=w["kappa"], dt=w["dt"], seed=w["seed"],
+                 species=[Species(q=-1.0, m=1.0, n_macro=n_sample),
+                          Species(q=1.0, m=w["mi"], T=w["Ti"], n_macro=n_sample)])
+    sim = Simulation(cfg)
+    sim.load(0)
+    sim.load(1)
+    sim.initialize_field()
+    t0 = time.perf_counter()
+    pushed = 0
+    for _ in range(steps):
+        pushed += sim.resident(0) + sim.resident(1)
+        sim.step()
+    dt = time.perf_counter() - t0
+    return pushed / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the particle loop of this build runs on a single MI355X "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synthetic_inputs import WORKLOADS
+    w = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    r32 = run_gpu(w, "fp32", args.steps, args.warmup, stream)
+    value = r32["particle_steps"] / r32["elapsed"]
+    tm = r32["timing"]
+    push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
+    per_launch = r32["particle_steps"] / max(tm["push_launches"], 1)
+    achieved = BYTES_PER_PARTICLE["fp32"] * per_launch / (push_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s (push+gather+deposit) on 1 MI355X, FP32 vs FP64; % HBM peak",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: alpha={w['alpha']}, wce/wpe={w['wce']}, grid {w['n1']}x{w['n2']}, "
+                               f"x1_out={w['x1_out']}, lambdaD/R0={w['kappa']}, mi/me={w['mi']}, Ti/Te={w['Ti']}, "
+                               f"{w['n_macro']:.0e} macro-particles per species, Maxwellian flux injection, "
+                               f"dt={w['dt']}/wpe; FP32 split push/gather/deposit, FP64 multigrid Poisson and tallies",
+                   "particles_per_species": w["n_macro"], "grid": [w["n1"], w["n2"]]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push_split", "avg_launch_ms": push_avg_ms,
+                     "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"]},
+        "breakdown_ms_per_step": {k: tm[k] / max(tm["steps"], 1) for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+        "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1),
+        "balance_exact": r32["balance_exact"],
+    }
+    if not args.no_fp64:
+        r64 = run_gpu(w, "fp64", args.steps, args.warmup, stream)
+        v64 = r64["particle_steps"] / r64["elapsed"]
+        t64 = r64["timing"]
+        a64 = t64["push_ms"] / max(t64["push_launches"], 1)
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["elapsed"] / args.steps,
+                       "push_avg_launch_ms": a64,
+                       "push_GBps": BYTES_PER_PARTICLE["fp64"] * r64["particle_steps"] / max(t64["push_launches"], 1)
+                       / (a64 * 1e-3) / 1e9}
+        out["speedup_fp32_vs_fp64"] = value / v64
+    if not args.no_cpu_baseline:
+        rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
+        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{args.workload} geometry, grid and field solve with "
+                                         f"{args.cpu_sample:.0e} macro-particles per species, {args.cpu_steps} full "
+                                         f"steps ({secs:.1f} s of CPU time; numpy oracle, one thread)"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,79 @@
+"""ctypes mirror of include/apic.h (structures, constants, prototypes)."""
+import ctypes as C
+import os
+
+APIC_OK, APIC_EINVAL, APIC_ERANGE, APIC_ENOMEM, APIC_EDEVICE, APIC_ESTATE = 0, -1, -2, -3, -4, -5
+APIC_FP32_SPLIT, APIC_FP64 = 0, 1
+APIC_MAX_SPECIES = 2
+
+ERROR_NAMES = {APIC_EINVAL: "APIC_EINVAL", APIC_ERANGE: "APIC_ERANGE", APIC_ENOMEM: "APIC_ENOMEM",
+               APIC_EDEVICE: "APIC_EDEVICE", APIC_ESTATE: "APIC_ESTATE"}
+
+
+class apic_species(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("T", C.c_double), ("n", C.c_double),
+                ("e_bind", C.c_double), ("weight", C.c_double), ("n_macro", C.c_int64),
+                ("capacity", C.c_int64)]
+
+
+class apic_grain_cfg(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("wce", C.c_double), ("kappa", C.c_double),
+                ("x1_out", C.c_double), ("phi_grain", C.c_double), ("phi_out", C.c_double),
+                ("dt", C.c_double), ("n1", C.c_int32), ("n2", C.c_int32), ("n_bins", C.c_int32),
+                ("n_species", C.c_int32), ("seed", C.c_uint64),
+                ("sp", apic_species * APIC_MAX_SPECIES)]
+
+
+class apic_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("inject", C.c_int32), ("frozen_field", C.c_int32),
+                ("sort_every", C.c_int32), ("poisson_tol", C.c_double),
+                ("poisson_max_cycles", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class apic_tally(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_bins", C.c_int32), ("steps", C.c_uint64),
+                ("injected", C.c_uint64 * APIC_MAX_SPECIES), ("absorbed", C.c_uint64 * APIC_MAX_SPECIES),
+                ("escaped", C.c_uint64 * APIC_MAX_SPECIES), ("resident", C.c_uint64 * APIC_MAX_SPECIES),
+                ("particle_steps", C.c_uint64 * APIC_MAX_SPECIES),
+                ("weight", C.c_double * APIC_MAX_SPECIES), ("F_el_sum", C.c_double),
+                ("count", C.POINTER(C.c_uint64)), ("charge", C.POINTER(C.c_double)),
+                ("pR", C.POINTER(C.c_double)), ("pZ", C.POINTER(C.c_double)),
+                ("L", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double))]
+
+
+class apic_kernel_times(C.Structure):
+    _fields_ = [("push_ms", C.c_double), ("inject_ms", C.c_double), ("sort_ms", C.c_double),
+                ("field_ms", C.c_double), ("push_launches", C.c_int64), ("steps", C.c_int64),
+                ("particle_steps", C.c_int64), ("mg_cycles", C.c_int64)]
+
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapic.so")
+
+# exported symbol -> (restype, argtypes)
+_D = C.POINTER(C.c_double)
+PROTOTYPES = {
+    "apic_init": (C.c_int, [C.POINTER(apic_grain_cfg), C.c_int32, C.POINTER(apic_opts), C.POINTER(C.c_void_p)]),
+    "apic_inject": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D, _D, _D]),
+    "apic_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "apic_solve_poisson": (C.c_int, [C.c_void_p, C.c_int32, _D, _D]),
+    "apic_tallies": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(apic_tally)]),
+    "apic_particles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D, _D, _D,
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "apic_fields": (C.c_int, [C.c_void_p, C.c_int32, _D, _D]),
+    "apic_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
+    "apic_timing": (C.c_int, [C.c_void_p, C.POINTER(apic_kernel_times)]),
+    "apic_free": (C.c_int, [C.c_void_p]),
+    "apic_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+
+def load(path=LIB_PATH):
+    """Loads libapic.so; raises if it has not been built."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with paper_2307_11107_amd.build.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib

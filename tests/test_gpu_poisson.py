@@ -1,0 +1,61 @@
+"""GPU parity of the FP64 Poisson solve (eqs. 6-7) against the oracle's LU solve
+on the same charge density, through the C ABI."""
+import numpy as np
+import pytest
+
+import paper_2307_11107_amd as apic
+from oracle.grid import Grid
+from oracle.poisson import PoissonSolver, source_from_density
+from synthetic_inputs import smooth_density
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(64, 64, 0.0, -0.1, 2.0), (64, 128, 0.15, -0.1, 1.0), (128, 64, -0.2, -0.3, 0.7),
+         (256, 256, 0.2, -0.1, 1.0), (512, 512, 0.2, -0.1, 1.0)]
+
+
+def _ctx(n1, n2, alpha, xo, kappa, precision=apic.APIC_FP64):
+    cfg = apic.grain_cfg(alpha, n1, n2, [apic.species(-1, 1, n_macro=0)], x1_out=xo, kappa=kappa)
+    return apic.apic_init([cfg], apic.opts(precision=precision, inject=False))
+
+
+@pytest.mark.parametrize("n1,n2,alpha,xo,kappa", CASES)
+def test_solve_matches_oracle(n1, n2, alpha, xo, kappa):
+    print(f"poisson parity n1={n1} n2={n2} alpha={alpha}", flush=True)
+    rho = smooth_density(n1, n2, seed=n1 + n2, amplitude=2.0)
+    ctx = _ctx(n1, n2, alpha, xo, kappa)
+    try:
+        phi = apic.apic_solve_poisson(ctx, 0, rho, shape=(n2 + 1, n1 + 1))
+    finally:
+        apic.apic_free(ctx)
+    g = Grid(n1, n2, xo, alpha)
+    ref = PoissonSolver(g).solve(source_from_density(rho, kappa), -2.5, 0.0)
+    err = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+    print(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.2])
+def test_vacuum_solution_linear_in_x1(alpha):
+    n1, n2 = 96, 64
+    ctx = _ctx(n1, n2, alpha, -0.1, 1.0)
+    try:
+        phi = apic.apic_solve_poisson(ctx, 0, np.zeros((n2 + 1, n1 + 1)), shape=(n2 + 1, n1 + 1))
+    finally:
+        apic.apic_free(ctx)
+    x1 = -1.0 + (0.9 / n1) * np.arange(n1 + 1)
+    lin = -2.5 + 2.5 * (x1 + 1.0) / 0.9
+    assert np.max(np.abs(phi - lin[None, :])) < 1e-11
+
+
+def test_fp32_context_solves_in_fp64():
+    """The split-precision loop keeps the field solve in FP64."""
+    n1, n2 = 64, 64
+    rho = smooth_density(n1, n2, seed=3)
+    ctx = _ctx(n1, n2, 0.1, -0.1, 1.0, precision=apic.APIC_FP32_SPLIT)
+    try:
+        phi = apic.apic_solve_poisson(ctx, 0, rho, shape=(n2 + 1, n1 + 1))
+    finally:
+        apic.apic_free(ctx)
+    ref = PoissonSolver(Grid(n1, n2, -0.1, 0.1)).solve(source_from_density(rho, 1.0), -2.5, 0.0)
+    assert np.max(np.abs(phi - ref)) / np.max(np.abs(ref)) <= 1e-10
