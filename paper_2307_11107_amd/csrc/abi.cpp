@@ -123,8 +123,7 @@ int solve_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_flo
     double r = std::sqrt(r2), prev = r;
     int c = 0;
     while (c < max_cycles && r > tol * bnorm) {
-        HIPCHK(ctx, mg_vcycle(ctx, g));
-        HIPCHK(ctx, mg_residual_norm(ctx, g, &g.ctr->norm2));
+        HIPCHK(ctx, mg_vcycle(ctx, g));   // also leaves the new residual norm in ctr->norm2
         TRY(read_norms(ctx, g, &r2, nullptr));
         r = std::sqrt(r2);
         ++c;
@@ -191,6 +190,8 @@ void free_grain(Grain& g) {
     F(g.sort_count);
     F(g.sort_offset);
     F(g.scan_tmp);
+    if (g.vcycle_exec) (void)hipGraphExecDestroy(g.vcycle_exec);
+    g.vcycle_exec = nullptr;
     for (auto& L : g.mg) {
         F(L.st);
         F(L.u);
@@ -298,9 +299,17 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
     TRY(alloc_t(ctx, &g.rho, (size_t)g.nodes));
     TRY(alloc_t(ctx, &g.tally, (size_t)5 * g.ns * gp.n_bins));
     TRY(alloc_t(ctx, &g.tally_count, (size_t)g.ns * gp.n_bins));
-    TRY(alloc_t(ctx, &g.sort_count, (size_t)g.ncells + 1));
-    TRY(alloc_t(ctx, &g.sort_offset, (size_t)g.ncells + 2));
-    g.scan_tmp_bytes = scan_temp_bytes(g.ncells + 1);
+    // sort tiles: the smallest square power-of-two tile giving at most 8192 tiles
+    gp.tile_log2 = 3;
+    while (((n1 + (1 << gp.tile_log2) - 1) >> gp.tile_log2) * ((n2 + (1 << gp.tile_log2) - 1) >> gp.tile_log2) > 8192)
+        ++gp.tile_log2;
+    gp.ntx = (n1 + (1 << gp.tile_log2) - 1) >> gp.tile_log2;
+    gp.ntiles = gp.ntx * ((n2 + (1 << gp.tile_log2) - 1) >> gp.tile_log2);
+    const size_t hist_len = (size_t)gp.ntiles * sort_blocks() + 1;
+    TRY(alloc_t(ctx, &g.sort_count, hist_len));
+    TRY(alloc_t(ctx, &g.sort_offset, hist_len));
+    HIPCHK(ctx, launch_fill(ctx, g.sort_count, sizeof(int) * hist_len));
+    g.scan_tmp_bytes = scan_temp_bytes((int)hist_len);
     TRY(dev_alloc(ctx, &g.scan_tmp, g.scan_tmp_bytes));
     HIPCHK(ctx, launch_fill(ctx, g.ctr, sizeof(DevCounters)));
     HIPCHK(ctx, launch_fill(ctx, g.tally, sizeof(double) * 5 * g.ns * gp.n_bins));
@@ -310,10 +319,12 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
                                hipMemcpyHostToDevice, ctx->stream));
 
     // ---- multigrid hierarchy
+    // coarsen by two while both cell counts are even and at least 8, and stop
+    // at the first level with at most 600 nodes (solved by a dense inverse)
     std::vector<Stencil> levels(1);
     fine_stencil(n1, n2, c.x1_out, c.alpha, levels[0]);
-    while (levels.back().n1 % 2 == 0 && levels.back().n2 % 2 == 0 &&
-           std::min(levels.back().n1, levels.back().n2) / 2 >= 4) {
+    while ((levels.back().n1 + 1) * (levels.back().n2 + 1) > 600 && levels.back().n1 % 2 == 0 &&
+           levels.back().n2 % 2 == 0 && std::min(levels.back().n1, levels.back().n2) / 2 >= 4) {
         Stencil cs;
         galerkin_coarse(levels.back(), cs);
         levels.push_back(std::move(cs));
@@ -433,7 +444,6 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         delete ctx;
         return fail(nullptr, APIC_EINVAL, "precision must be APIC_FP32_SPLIT or APIC_FP64");
     }
-    ctx->stream = static_cast<hipStream_t>(ctx->opts.stream);
     int rc = APIC_OK;
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -442,11 +452,23 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         delete ctx;
         return APIC_EDEVICE;
     }
+    ctx->stream = static_cast<hipStream_t>(ctx->opts.stream);
+    if (!ctx->stream) {
+        // the legacy default stream cannot be captured into graphs: use our own
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_init_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            delete ctx;
+            return APIC_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
     ctx->grains.resize(n_grains);
     for (int i = 0; i < n_grains && rc == APIC_OK; ++i) rc = setup_grain(ctx, ctx->grains[i], cfgs[i], i);
     if (rc != APIC_OK) {
         g_init_error = ctx->err;
         for (auto& g : ctx->grains) free_grain(g);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
         return rc;
     }
@@ -707,6 +729,7 @@ int apic_free(apic_ctx* ctx) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return APIC_OK;
 }

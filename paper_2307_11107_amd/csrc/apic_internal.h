@@ -30,6 +30,7 @@ struct GrainParams {
     double r_grain_max;         // largest radius of the grain surface
     double M_vol, M_area;       // rejection bounds for loading / injection
     uint32_t key0, key1;        // Philox key
+    int tile_log2, ntx, ntiles; // sort tiles: 2^tile_log2 cells square, ntx per row
 };
 
 // Device counters of one grain (one allocation, zeroed at init).
@@ -100,9 +101,10 @@ struct Grain {
     int coarse_nodes = 0;
     double bnd_norm2 = 0;           // |A_interior,boundary u_boundary|^2 (host)
     std::vector<MGLevel> mg;
+    hipGraphExec_t vcycle_exec = nullptr;   // captured V-cycle
     // sort scratch
-    int* sort_count = nullptr;      // ncells + 1
-    int* sort_offset = nullptr;     // ncells + 2
+    int* sort_count = nullptr;      // per-block tile histograms, ntiles * sort_blocks + 1
+    int* sort_offset = nullptr;     // their exclusive scan
     void* scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
 };
@@ -115,6 +117,8 @@ struct apic_ctx {
     std::vector<apic::Grain> grains;
     apic_opts opts;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool graphs = true;                     // capture repeated launch sequences
     int device = 0;
     int num_cus = 256;
     std::string err;
@@ -142,6 +146,7 @@ hipError_t launch_sort(apic_ctx* ctx, Grain& g, int s);
 hipError_t launch_add_slots(apic_ctx* ctx, Grain& g, int s, int64_t n_new);
 hipError_t launch_count_live(apic_ctx* ctx, Grain& g, int s, unsigned long long* out);
 size_t scan_temp_bytes(int n);
+int sort_blocks();
 
 // field.hip
 hipError_t launch_fill(apic_ctx* ctx, void* p, size_t bytes);

@@ -4,40 +4,43 @@
 // the same discrete system is solved by multigrid V-cycles: Galerkin coarse
 // operators (R A P, bilinear P, R = P^T / 4, built on the host), alternating
 // zebra line Gauss-Seidel smoothing (x1-lines, then x2-lines; each line is a
-// tridiagonal system solved in LDS by parallel cyclic reduction, one workgroup
-// per line), and a dense inverse on the coarsest grid.  The operator's
-// anisotropy changes direction across the domain (the x1 coefficient falls
-// like r^-4), which is why both line directions are relaxed.
+// tridiagonal system solved in LDS by parallel cyclic reduction), and a dense
+// inverse on the coarsest grid (at most a few hundred nodes).  The operator's
+// anisotropy changes direction across the domain (the x1 coefficient falls like
+// r^-4), which is why both line directions are relaxed.  One V-cycle is
+// captured once into a HIP graph and replayed.
 #include "apic_internal.h"
 
 namespace apic {
 
 constexpr int MG_BLOCK = 256;
 
-// Parallel cyclic reduction on a tridiagonal system held in LDS (a: sub, b:
-// diagonal, c: super, d: rhs; a[0] = c[n-1] = 0).  Each thread owns up to K
-// equations.  On return d[i] / b[i] is the solution.
+// Parallel cyclic reduction on a set of tridiagonal systems held in LDS (a:
+// sub, b: diagonal, c: super, d: rhs).  Equation e belongs to system e / L and
+// couples only inside its system; a[first] = c[last] = 0.  Each thread owns up
+// to K equations.  On return d[e] / b[e] is the solution.
 template <int K>
-__device__ void pcr_solve(double* a, double* b, double* c, double* d, int n) {
-    for (int s = 1; s < n; s <<= 1) {
+__device__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int total) {
+    for (int s = 1; s < L; s <<= 1) {
         double na[K], nb[K], nc[K], nd[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * MG_BLOCK;
-            if (i < n) {
-                double ai = a[i], bi = b[i], ci = c[i], di = d[i];
+            const int e = threadIdx.x + k * MG_BLOCK;
+            if (e < total) {
+                const int j = e % L;
+                double ai = a[e], bi = b[e], ci = c[e], di = d[e];
                 double an = 0.0, cn = 0.0;
-                if (i - s >= 0) {
-                    const double m = ai / b[i - s];
-                    bi -= m * c[i - s];
-                    di -= m * d[i - s];
-                    an = -m * a[i - s];
+                if (j - s >= 0) {
+                    const double m = ai / b[e - s];
+                    bi -= m * c[e - s];
+                    di -= m * d[e - s];
+                    an = -m * a[e - s];
                 }
-                if (i + s < n) {
-                    const double m = ci / b[i + s];
-                    bi -= m * a[i + s];
-                    di -= m * d[i + s];
-                    cn = -m * c[i + s];
+                if (j + s < L) {
+                    const double m = ci / b[e + s];
+                    bi -= m * a[e + s];
+                    di -= m * d[e + s];
+                    cn = -m * c[e + s];
                 }
                 na[k] = an;
                 nb[k] = bi;
@@ -48,12 +51,12 @@ __device__ void pcr_solve(double* a, double* b, double* c, double* d, int n) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * MG_BLOCK;
-            if (i < n) {
-                a[i] = na[k];
-                b[i] = nb[k];
-                c[i] = nc[k];
-                d[i] = nd[k];
+            const int e = threadIdx.x + k * MG_BLOCK;
+            if (e < total) {
+                a[e] = na[k];
+                b[e] = nb[k];
+                c[e] = nc[k];
+                d[e] = nd[k];
             }
         }
         __syncthreads();
@@ -76,6 +79,20 @@ __host__ __device__ inline StencilPtrs stencil_ptrs(const double* st, int nodes)
     p.NW = st + ST_NW * (size_t)nodes;
     p.NE = st + ST_NE * (size_t)nodes;
     return p;
+}
+
+// (A u) at an unknown node (j, i) of a level; nn / ss carry the finest level's
+// second-neighbour axis couplings (null on coarse levels).
+__device__ inline double apply_A(const StencilPtrs& p, const double* __restrict__ nn,
+                                 const double* __restrict__ ss, const double* __restrict__ u, int n2,
+                                 int nx, int j, int i) {
+    const size_t o = (size_t)j * nx + i;
+    double au = p.C[o] * u[o] + p.W[o] * u[o - 1] + p.E[o] * u[o + 1];
+    if (j > 0) au += p.S[o] * u[o - nx] + p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
+    if (j < n2) au += p.N[o] * u[o + nx] + p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
+    if (nn && j == 0) au += nn[i] * u[o + 2 * nx];
+    if (ss && j == n2) au += ss[i] * u[o - 2 * nx];
+    return au;
 }
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
@@ -111,105 +128,122 @@ k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
         d[k] = rhs;
     }
     __syncthreads();
-    pcr_solve<K>(a, b, c, d, L);
+    pcr_solve<K>(a, b, c, d, L, L);
     for (int k = threadIdx.x; k < L; k += MG_BLOCK) u[(size_t)j * nx + k + 1] = d[k] / b[k];
 }
 
-// Relaxation of the lines i1 = i (i = 1 + color, 3 + color, ...): unknowns
-// i2 = 0..n2.  On the finest level the axis rows carry a second-neighbour
-// coupling (one-sided d/dx2); it is eliminated with the adjacent row so the
-// line stays tridiagonal.
-template <int K>
+// Relaxation of LPB lines i1 = i (i = 1 + color, 3 + color, ...) per workgroup:
+// unknowns i2 = 0..n2.  Neighbouring lines of one colour are read together so
+// that the row-wise loads stay within a cache line.  On the finest level the
+// axis rows carry a second-neighbour coupling (one-sided d/dx2); it is
+// eliminated with the adjacent row so each line stays tridiagonal.
+template <int K, int LPB>
 __global__ void __launch_bounds__(MG_BLOCK)
 k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
            const double* __restrict__ nn, const double* __restrict__ ss, double* __restrict__ u,
            const double* __restrict__ f) {
     extern __shared__ double lds[];
     const int L = n2 + 1;
+    const int total = LPB * L;
     double* a = lds;
-    double* b = a + L;
-    double* c = b + L;
-    double* d = c + L;
-    const int i = 1 + color + 2 * blockIdx.x;
-    if (i > n1 - 1) return;
+    double* b = a + total;
+    double* c = b + total;
+    double* d = c + total;
+    const int i0 = 1 + color + 2 * LPB * blockIdx.x;
+    if (i0 > n1 - 1) return;
     const int nx = n1 + 1;
     const StencilPtrs p = stencil_ptrs(st, nodes);
-    for (int j = threadIdx.x; j < L; j += MG_BLOCK) {
+    for (int q = threadIdx.x; q < total; q += MG_BLOCK) {
+        const int m = q % LPB, j = q / LPB;
+        const int i = i0 + 2 * m;
+        const int e = m * L + j;
+        if (i > n1 - 1) {
+            a[e] = 0.0;
+            b[e] = 1.0;
+            c[e] = 0.0;
+            d[e] = 0.0;
+            continue;
+        }
         const size_t o = (size_t)j * nx + i;
         double rhs = f[o] - p.W[o] * u[o - 1] - p.E[o] * u[o + 1];
         if (j > 0) rhs -= p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
         if (j < n2) rhs -= p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
-        a[j] = j > 0 ? p.S[o] : 0.0;
-        b[j] = p.C[o];
-        c[j] = j < n2 ? p.N[o] : 0.0;
-        d[j] = rhs;
+        a[e] = j > 0 ? p.S[o] : 0.0;
+        b[e] = p.C[o];
+        c[e] = j < n2 ? p.N[o] : 0.0;
+        d[e] = rhs;
     }
     __syncthreads();
-    if (nn && threadIdx.x == 0) {
-        const double m = nn[i] / c[1];
-        b[0] -= m * a[1];
-        c[0] -= m * b[1];
-        d[0] -= m * d[1];
+    if (threadIdx.x < LPB && nn) {
+        const int m = threadIdx.x, i = i0 + 2 * m;
+        if (i <= n1 - 1) {
+            const int e = m * L;
+            const double mm = nn[i] / c[e + 1];
+            b[e] -= mm * a[e + 1];
+            c[e] -= mm * b[e + 1];
+            d[e] -= mm * d[e + 1];
+        }
     }
-    if (ss && threadIdx.x == 1) {
-        const double m = ss[i] / a[n2 - 1];
-        a[n2] -= m * b[n2 - 1];
-        b[n2] -= m * c[n2 - 1];
-        d[n2] -= m * d[n2 - 1];
+    if (threadIdx.x >= 64 && threadIdx.x < 64 + LPB && ss) {
+        const int m = threadIdx.x - 64, i = i0 + 2 * m;
+        if (i <= n1 - 1) {
+            const int e = m * L + n2;
+            const double mm = ss[i] / a[e - 1];
+            a[e] -= mm * b[e - 1];
+            b[e] -= mm * c[e - 1];
+            d[e] -= mm * d[e - 1];
+        }
     }
     __syncthreads();
-    pcr_solve<K>(a, b, c, d, L);
-    for (int j = threadIdx.x; j < L; j += MG_BLOCK) u[(size_t)j * nx + i] = d[j] / b[j];
+    pcr_solve<K>(a, b, c, d, L, total);
+    for (int q = threadIdx.x; q < total; q += MG_BLOCK) {
+        const int m = q % LPB, j = q / LPB;
+        const int i = i0 + 2 * m;
+        if (i > n1 - 1) continue;
+        const int e = m * L + j;
+        u[(size_t)j * nx + i] = d[e] / b[e];
+    }
 }
 
-// r = f - A u on the unknown nodes, 0 on the Dirichlet columns; optionally
-// accumulates |D^-1 r|^2 (D = diagonal of A): the operator's rows differ in
-// scale by ~r^4, and the row-scaled norm weighs every node alike.
-__global__ void __launch_bounds__(MG_BLOCK)
-k_residual(int n1, int n2, const double* __restrict__ st, int nodes, const double* __restrict__ nn,
-           const double* __restrict__ ss, const double* __restrict__ u,
-           const double* __restrict__ f, double* __restrict__ r, double* norm2) {
+// Block sum of a per-thread value, one atomic per block.
+__device__ inline void block_sum_add(double v, double* dst) {
     __shared__ double red[MG_BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < MG_BLOCK / 64; ++w) t += red[w];
+        atomicAdd(dst, t);
+    }
+}
+
+// |D^-1 (f - A u)|^2 over the unknown nodes of the finest level (D = diagonal
+// of A): the operator's rows differ in scale by ~r^4, and the row-scaled norm
+// weighs every node alike.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_residual_norm(int n1, int n2, const double* __restrict__ st, int nodes,
+                const double* __restrict__ nn, const double* __restrict__ ss,
+                const double* __restrict__ u, const double* __restrict__ f, double* norm2) {
     const int nx = n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     double rr = 0.0;
     if (idx < nodes) {
         const int j = idx / nx, i = idx - j * nx;
-        double v = 0.0;
         if (i > 0 && i < n1) {
             const StencilPtrs p = stencil_ptrs(st, nodes);
-            const size_t o = idx;
-            double au = p.C[o] * u[o] + p.W[o] * u[o - 1] + p.E[o] * u[o + 1];
-            if (j > 0) au += p.S[o] * u[o - nx] + p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
-            if (j < n2) au += p.N[o] * u[o + nx] + p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
-            if (nn && j == 0) au += nn[i] * u[o + 2 * nx];
-            if (ss && j == n2) au += ss[i] * u[o - 2 * nx];
-            v = f[o] - au;
-        }
-        if (r) r[idx] = v;
-        if (i > 0 && i < n1) {
-            const double q = v / st[ST_C * (size_t)nodes + idx];
+            const double q = (f[idx] - apply_A(p, nn, ss, u, n2, nx, j, i)) / p.C[idx];
             rr = q * q;
         }
     }
-    if (norm2) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < MG_BLOCK / 64; ++w) t += red[w];
-            atomicAdd(norm2, t);
-        }
-    }
+    block_sum_add(rr, norm2);
 }
 
 // |D^-1 f|^2 over the unknown nodes
 __global__ void __launch_bounds__(MG_BLOCK)
 k_rhs_norm(int n1, int nodes, const double* __restrict__ diag, const double* __restrict__ f,
            double* norm2) {
-    __shared__ double red[MG_BLOCK / 64];
     const int nx = n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     double v = 0.0;
@@ -220,34 +254,39 @@ k_rhs_norm(int n1, int nodes, const double* __restrict__ diag, const double* __r
             v = q * q;
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < MG_BLOCK / 64; ++w) t += red[w];
-        atomicAdd(norm2, t);
-    }
+    block_sum_add(v, norm2);
 }
 
-// coarse f = P^T r / 4 on the coarse unknowns (full weighting without the
-// rows outside the grid), 0 on the coarse Dirichlet columns
+// Coarse right-hand side fc = P^T (f - A u) / 4 on the coarse unknowns, the
+// fine residuals formed on the fly (full weighting without rows outside the
+// grid); fc = 0 on the coarse Dirichlet columns; the coarse correction uc is
+// cleared.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_restrict(int n1f, int n2f, int n1c, int n2c, const double* __restrict__ rf,
-           double* __restrict__ fc) {
+k_restrict_residual(int n1f, int n2f, const double* __restrict__ st, int nodes_f,
+                    const double* __restrict__ nn, const double* __restrict__ ss,
+                    const double* __restrict__ u, const double* __restrict__ f, int n1c, int n2c,
+                    double* __restrict__ fc, double* __restrict__ uc) {
     const int nxc = n1c + 1, nxf = n1f + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     if (idx >= nxc * (n2c + 1)) return;
+    uc[idx] = 0.0;
     const int J = idx / nxc, I = idx - J * nxc;
-    if (I == 0 || I == n1c) { fc[idx] = 0.0; return; }
+    if (I == 0 || I == n1c) {
+        fc[idx] = 0.0;
+        return;
+    }
+    const StencilPtrs p = stencil_ptrs(st, nodes_f);
     double acc = 0.0;
     for (int dj = -1; dj <= 1; ++dj) {
         const int j = 2 * J + dj;
         if (j < 0 || j > n2f) continue;
         const double wj = dj == 0 ? 1.0 : 0.5;
-        const double* row = rf + (size_t)j * nxf + 2 * I;
-        acc += wj * (0.5 * row[-1] + row[0] + 0.5 * row[1]);
+        for (int di = -1; di <= 1; ++di) {
+            const int i = 2 * I + di;      // 1 <= i <= n1f - 1
+            const double wi = di == 0 ? 1.0 : 0.5;
+            const double r = f[(size_t)j * nxf + i] - apply_A(p, nn, ss, u, n2f, nxf, j, i);
+            acc += wj * wi * r;
+        }
     }
     fc[idx] = 0.25 * acc;
 }
@@ -268,65 +307,97 @@ k_prolong_add(int n1f, int n2f, int n1c, const double* __restrict__ uc, double* 
     uf[idx] += v;
 }
 
-// coarsest grid: u = A^-1 f (dense inverse with identity Dirichlet rows)
+// coarsest grid: u = A^-1 f (dense inverse with identity Dirichlet rows), one
+// wave per row
 __global__ void __launch_bounds__(MG_BLOCK)
 k_coarse_solve(int m, const double* __restrict__ inv, const double* __restrict__ f,
                double* __restrict__ u) {
-    const int row = blockIdx.x * MG_BLOCK + threadIdx.x;
+    const int row = blockIdx.x * (MG_BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (row >= m) return;
     const double* a = inv + (size_t)row * m;
     double acc = 0.0;
-    for (int k = 0; k < m; ++k) acc += a[k] * f[k];
-    u[row] = acc;
+    for (int k = lane; k < m; k += 64) acc += a[k] * f[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) u[row] = acc;
 }
 
 template <int K>
-static void relax_level(apic_ctx* ctx, Grain& g, int l) {
-    MGLevel& L = g.mg[l];
-    const double* nn = l == 0 ? g.axis_nn : nullptr;
-    const double* ss = l == 0 ? g.axis_ss : nullptr;
-    const size_t lds1 = 4 * sizeof(double) * (size_t)(L.n1 - 1);
-    const size_t lds2 = 4 * sizeof(double) * (size_t)(L.n2 + 1);
-    for (int color = 0; color < 2; ++color) {
-        const int lines = (L.n2 + 1 - color + 1) / 2;
-        hipLaunchKernelGGL(k_relax_x1<K>, dim3(lines), dim3(MG_BLOCK), lds1, ctx->stream, L.n1,
-                           L.n2, color, L.st, L.nodes, nn, ss, L.u, L.f);
-    }
-    for (int color = 0; color < 2; ++color) {
-        const int lines = (L.n1 - 1 - color + 1) / 2;
-        if (lines <= 0) continue;
-        hipLaunchKernelGGL(k_relax_x2<K>, dim3(lines), dim3(MG_BLOCK), lds2, ctx->stream, L.n1,
-                           L.n2, color, L.st, L.nodes, nn, ss, L.u, L.f);
+static void relax_x1(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+    const size_t lds = 4 * sizeof(double) * (size_t)(L.n1 - 1);
+    const int lines = (L.n2 + 1 - color + 1) / 2;
+    hipLaunchKernelGGL(k_relax_x1<K>, dim3(lines), dim3(MG_BLOCK), lds, ctx->stream, L.n1, L.n2,
+                       color, L.st, L.nodes, nn, ss, L.u, L.f);
+}
+
+template <int K, int LPB>
+static void relax_x2(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+    const size_t lds = 4 * sizeof(double) * (size_t)LPB * (L.n2 + 1);
+    const int lines = (L.n1 - 1 - color + 1) / 2;
+    if (lines <= 0) return;
+    const int blocks = (lines + LPB - 1) / LPB;
+    hipLaunchKernelGGL((k_relax_x2<K, LPB>), dim3(blocks), dim3(MG_BLOCK), lds, ctx->stream, L.n1,
+                       L.n2, color, L.st, L.nodes, nn, ss, L.u, L.f);
+}
+
+// Lines of one colour per workgroup for the x2 sweeps: as many as fit in 64 KB
+// of LDS (four FP64 arrays per line) and in eight equations per thread.
+static int x2_lines_per_block(int L) {
+    if (16 * 8 * (size_t)L <= 65536 && 4 * L <= 8 * MG_BLOCK) return 4;
+    if (8 * 8 * (size_t)L <= 65536 && 2 * L <= 8 * MG_BLOCK) return 2;
+    return 1;
+}
+
+static int pcr_k(int total) {
+    const int k = (total + MG_BLOCK - 1) / MG_BLOCK;
+    return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8;
+}
+
+template <int LPB>
+static void relax_x2_k(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+    switch (pcr_k(LPB * (L.n2 + 1))) {
+        case 1: relax_x2<1, LPB>(ctx, L, nn, ss, color); break;
+        case 2: relax_x2<2, LPB>(ctx, L, nn, ss, color); break;
+        case 4: relax_x2<4, LPB>(ctx, L, nn, ss, color); break;
+        default: relax_x2<8, LPB>(ctx, L, nn, ss, color); break;
     }
 }
 
 static void relax(apic_ctx* ctx, Grain& g, int l) {
     const MGLevel& L = g.mg[l];
-    const int longest = std::max(L.n1 - 1, L.n2 + 1);
-    const int K = (longest + MG_BLOCK - 1) / MG_BLOCK;
-    if (K <= 1) relax_level<1>(ctx, g, l);
-    else if (K <= 2) relax_level<2>(ctx, g, l);
-    else if (K <= 4) relax_level<4>(ctx, g, l);
-    else relax_level<8>(ctx, g, l);
+    const double* nn = l == 0 ? g.axis_nn : nullptr;
+    const double* ss = l == 0 ? g.axis_ss : nullptr;
+    for (int color = 0; color < 2; ++color) {
+        switch (pcr_k(L.n1 - 1)) {
+            case 1: relax_x1<1>(ctx, L, nn, ss, color); break;
+            case 2: relax_x1<2>(ctx, L, nn, ss, color); break;
+            case 4: relax_x1<4>(ctx, L, nn, ss, color); break;
+            default: relax_x1<8>(ctx, L, nn, ss, color); break;
+        }
+    }
+    const int lpb = x2_lines_per_block(L.n2 + 1);
+    for (int color = 0; color < 2; ++color) {
+        if (lpb == 4) relax_x2_k<4>(ctx, L, nn, ss, color);
+        else if (lpb == 2) relax_x2_k<2>(ctx, L, nn, ss, color);
+        else relax_x2_k<1>(ctx, L, nn, ss, color);
+    }
 }
 
-hipError_t mg_vcycle(apic_ctx* ctx, Grain& g) {
+static void vcycle_launches(apic_ctx* ctx, Grain& g) {
     const int nl = (int)g.mg.size();
     for (int l = 0; l + 1 < nl; ++l) {
         MGLevel& F = g.mg[l];
         MGLevel& C = g.mg[l + 1];
         relax(ctx, g, l);
-        hipLaunchKernelGGL(k_residual, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                           ctx->stream, F.n1, F.n2, F.st, F.nodes, l == 0 ? g.axis_nn : nullptr,
-                           l == 0 ? g.axis_ss : nullptr, F.u, F.f, F.r, nullptr);
-        hipLaunchKernelGGL(k_restrict, dim3((C.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                           ctx->stream, F.n1, F.n2, C.n1, C.n2, F.r, C.f);
-        hipError_t e = launch_fill(ctx, C.u, sizeof(double) * (size_t)C.nodes);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_restrict_residual, dim3((C.nodes + MG_BLOCK - 1) / MG_BLOCK),
+                           dim3(MG_BLOCK), 0, ctx->stream, F.n1, F.n2, F.st, F.nodes,
+                           l == 0 ? g.axis_nn : nullptr, l == 0 ? g.axis_ss : nullptr, F.u, F.f,
+                           C.n1, C.n2, C.f, C.u);
     }
     MGLevel& B = g.mg[nl - 1];
-    hipLaunchKernelGGL(k_coarse_solve, dim3((B.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                       ctx->stream, B.nodes, g.coarse_inv, B.f, B.u);
+    hipLaunchKernelGGL(k_coarse_solve, dim3((B.nodes + MG_BLOCK / 64 - 1) / (MG_BLOCK / 64)),
+                       dim3(MG_BLOCK), 0, ctx->stream, B.nodes, g.coarse_inv, B.f, B.u);
     for (int l = nl - 2; l >= 0; --l) {
         MGLevel& F = g.mg[l];
         MGLevel& C = g.mg[l + 1];
@@ -334,6 +405,35 @@ hipError_t mg_vcycle(apic_ctx* ctx, Grain& g) {
                            0, ctx->stream, F.n1, F.n2, C.n1, C.u, F.u);
         relax(ctx, g, l);
     }
+    // row-scaled residual norm of the result
+    MGLevel& F = g.mg[0];
+    (void)launch_fill(ctx, &g.ctr->norm2, sizeof(double));
+    hipLaunchKernelGGL(k_residual_norm, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
+                       ctx->stream, F.n1, F.n2, F.st, F.nodes, g.axis_nn, g.axis_ss, F.u, F.f,
+                       &g.ctr->norm2);
+}
+
+// One V-cycle followed by the residual norm into ctr->norm2.  The launch
+// sequence is captured once into a graph (when the stream can be captured)
+// and replayed afterwards.
+hipError_t mg_vcycle(apic_ctx* ctx, Grain& g) {
+    if (!g.vcycle_exec && ctx->graphs) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            vcycle_launches(ctx, g);
+            e = hipStreamEndCapture(ctx->stream, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.vcycle_exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            g.vcycle_exec = nullptr;
+            ctx->graphs = false;
+        }
+    }
+    if (g.vcycle_exec) return hipGraphLaunch(g.vcycle_exec, ctx->stream);
+    vcycle_launches(ctx, g);
     return hipGetLastError();
 }
 
@@ -341,9 +441,9 @@ hipError_t mg_residual_norm(apic_ctx* ctx, Grain& g, double* norm2_dev) {
     MGLevel& F = g.mg[0];
     hipError_t e = launch_fill(ctx, norm2_dev, sizeof(double));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_residual, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
+    hipLaunchKernelGGL(k_residual_norm, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
                        ctx->stream, F.n1, F.n2, F.st, F.nodes, g.axis_nn, g.axis_ss, F.u, F.f,
-                       nullptr, norm2_dev);
+                       norm2_dev);
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <type_traits>
+
 namespace apic {
 
 constexpr int BLOCK = 256;
@@ -56,7 +58,7 @@ __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
 // t = 0 (outside) and t_in (inside); tallies at the impact point with the
 // velocity rotated into the impact point's meridional plane.
 template <typename T>
-__device__ void tally_impact(const GrainParams& gp, const SpeciesParams& sp, int s, int ns,
+__device__ __attribute__((noinline)) void tally_impact(const GrainParams& gp, const SpeciesParams& sp, int s, int ns,
                              T R, T Z, T dX, T dY, T dZ, T t_in, T vR, T vZ, T vT,
                              double* tally, unsigned long long* tally_count, int iters) {
     const T alpha = (T)gp.alpha;
@@ -96,8 +98,10 @@ __device__ void tally_impact(const GrainParams& gp, const SpeciesParams& sp, int
 template <typename T>
 __device__ inline T chord_inside(const GrainParams& gp, T R, T Z, T dX, T dY, T dZ) {
     const T dd = dX * dX + dY * dY + dZ * dZ;
-    if (!(dd > T(0))) return T(-1);
-    const T tc = -(R * dX + Z * dZ) / dd;
+    const T pd = -(R * dX + Z * dZ);
+    // the closest approach lies strictly inside the step only if 0 < pd < dd
+    if (!(pd > T(0) && pd < dd)) return T(-1);
+    const T tc = pd / dd;
     if (!(tc > T(0) && tc < T(1))) return T(-1);
     const T X = R + tc * dX, Y = tc * dY, Zc = Z + tc * dZ;
     const T rc2 = X * X + Y * Y + Zc * Zc;
@@ -109,154 +113,170 @@ __device__ inline T chord_inside(const GrainParams& gp, T R, T Z, T dX, T dY, T 
 }
 
 // ----------------------------------------------------------------- FP32 split push
-__global__ void __launch_bounds__(BLOCK)
-k_push_split(GrainParams gp, SpeciesParams sp, int s, int ns,
-             int32_t* __restrict__ cell, float* __restrict__ f1a, float* __restrict__ f2a,
-             float* __restrict__ vRa, float* __restrict__ vZa, float* __restrict__ vTa,
-             const float2* __restrict__ grad, float* __restrict__ dep,
-             DevCounters* __restrict__ ctr, double* __restrict__ tally,
-             unsigned long long* __restrict__ tally_count) {
-    const int64_t n = ctr->n[s];
-    const int n1 = gp.n1, n2 = gp.n2, nx = gp.nx;
-    const float alpha = (float)gp.alpha;
-    const float h1 = (float)gp.h1, h2 = (float)gp.h2;
-    const float ih1 = (float)gp.inv_h1, ih2 = (float)gp.inv_h2;
-    const float mx1_out = (float)(-gp.x1_out);
-    const float step = (float)gp.step;
-    const float qmh = (float)sp.qm_half;
-    const float rcm1 = (float)sp.rot_cm1, rs = (float)sp.rot_s;
-    uint32_t n_live = 0, n_abs = 0, n_esc = 0;
+// Hardware reciprocal and square root (about 1 ulp) replace the correctly
+// rounded FP32 division and sqrt sequences in the split kernel; the position
+// update is formed from differences, so 1-ulp factors perturb a displacement
+// only by ~1e-7 of itself.
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = cell[p];
-        if (c < 0) continue;
-        ++n_live;
-        const int i1 = cell_i1(c), i2 = cell_i2(c);
-        const float f1 = f1a[p], f2 = f2a[p];
-        float vR = vRa[p], vZ = vZa[p], vT = vTa[p];
+// One particle of the FP32 split form.  Returns -1 for a dead slot, 0 if the
+// particle stays (new cell and offsets in i1n, i2n, f1n, f2n), 1 if absorbed,
+// 2 if escaped; the particle's slot is updated in place.
+struct SplitConsts {
+    int n1, n2, nx;
+    float alpha, h1, h2, ih1, ih2, mx1_out, step, qmh, rcm1, rs;
+};
 
-        // gather (bilinear in the logical coordinates)
-        const int idx = i2 * nx + i1;
-        const float2 g00 = grad[idx], g10 = grad[idx + 1];
-        const float2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
-        const float e1 = 1.f - f1, e2 = 1.f - f2;
-        const float w00 = e1 * e2, w10 = f1 * e2, w01 = e1 * f2, w11 = f1 * f2;
-        const float p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
-        const float p2 = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
+__device__ inline SplitConsts split_consts(const GrainParams& gp, const SpeciesParams& sp) {
+    SplitConsts k;
+    k.n1 = gp.n1;
+    k.n2 = gp.n2;
+    k.nx = gp.nx;
+    k.alpha = (float)gp.alpha;
+    k.h1 = (float)gp.h1;
+    k.h2 = (float)gp.h2;
+    k.ih1 = (float)gp.inv_h1;
+    k.ih2 = (float)gp.inv_h2;
+    k.mx1_out = (float)(-gp.x1_out);
+    k.step = (float)gp.step;
+    k.qmh = (float)sp.qm_half;
+    k.rcm1 = (float)sp.rot_cm1;
+    k.rs = (float)sp.rot_s;
+    return k;
+}
 
-        // geometry at the particle from the cell index: -x1 measured from the
-        // outer boundary (no cancellation where |x1| is small), 1 + x2 and 1 - x2
-        // measured from the two axis ends
-        const float x1 = -(mx1_out + ((float)(n1 - i1) - f1) * h1);
-        const float opx2 = ((float)i2 + f2) * h2;
-        const float omx2 = ((float)(n2 - i2) - f2) * h2;
-        const float x2 = 0.5f * (opx2 - omx2);
-        const float sn = sqrtf(opx2 * omx2);
-        const float r = r_of(x1, x2, alpha);
-        const float R = r * sn, Z = r * x2;
-        const Metric<float> m = metric_at(r, x2, sn, alpha);
-        const float ER = -(m.x1R * p1 + m.x2R * p2);
-        const float EZ = -(m.x1Z * p1 + m.x2Z * p2);
+__device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams& sp,
+                                     const SplitConsts& K, int s, int ns, int64_t p,
+                                     int32_t* __restrict__ cell, float* __restrict__ f1a,
+                                     float* __restrict__ f2a, float* __restrict__ vRa,
+                                     float* __restrict__ vZa, float* __restrict__ vTa,
+                                     const float2* __restrict__ grad, double* __restrict__ tally,
+                                     unsigned long long* __restrict__ tally_count, int& i1n,
+                                     int& i2n, float& f1n, float& f2n) {
+    const int32_t c = cell[p];
+    if (c < 0) return -1;
+    const int n1 = K.n1, n2 = K.n2, nx = K.nx;
+    const float alpha = K.alpha, h1 = K.h1, h2 = K.h2, qmh = K.qmh, step = K.step;
+    const int i1 = cell_i1(c), i2 = cell_i2(c);
+    const float f1 = f1a[p], f2 = f2a[p];
+    float vR = vRa[p], vZ = vZa[p], vT = vTa[p];
 
-        // Boris kick (eq. 9: dV_R = -omega V_Theta dt, dV_Theta = +omega V_R dt).
-        // The rotation is applied as v + ((cos - 1) v + sin v_perp) with cos - 1
-        // held separately, so its FP32 form preserves |v| to ~1e-10 per step
-        // instead of drifting by the rounding of cos.
-        vR += qmh * ER;
-        vZ += qmh * EZ;
-        {
-            const float t = vR + (rcm1 * vR - rs * vT);
-            vT = vT + (rs * vR + rcm1 * vT);
-            vR = t;
-        }
-        vR += qmh * ER;
-        vZ += qmh * EZ;
+    // gather (bilinear in the logical coordinates)
+    const int idx = i2 * nx + i1;
+    const float2 g00 = grad[idx], g10 = grad[idx + 1];
+    const float2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
+    const float e1 = 1.f - f1, e2 = 1.f - f2;
+    const float w00 = e1 * e2, w10 = f1 * e2, w01 = e1 * f2, w11 = f1 * f2;
+    const float p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
+    const float p2 = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
 
-        // drift in the local Cartesian frame
-        const float dX = step * vR, dY = step * vT, dZ = step * vZ;
-        const float X = R + dX, Zn = Z + dZ;
-        const float Rn2 = X * X + dY * dY;
-        const float Rn = sqrtf(Rn2);
-        // rotation of (v_R, v_Theta) into the new meridional plane, again as
-        // v + ((cos - 1) v + sin v_perp) with cos - 1 = -dY^2 / (R' (X + R'))
-        float cm = 0.f, sr = 0.f;
-        if (Rn > 0.f) {
-            const float iR = 1.f / Rn;
-            sr = dY * iR;
-            cm = X > 0.f ? -(dY * dY) * iR / (X + Rn) : X * iR - 1.f;
-        }
-        const float vRn = vR + (cm * vR + sr * vT);
-        const float vTn = vT + (-sr * vR + cm * vT);
+    // geometry at the particle from the cell index: -x1 measured from the
+    // outer boundary (no cancellation where |x1| is small), 1 + x2 and 1 - x2
+    // measured from the two axis ends
+    const float mx1 = K.mx1_out + ((float)(n1 - i1) - f1) * h1;      // -x1 > 0
+    const float opx2 = ((float)i2 + f2) * h2;
+    const float omx2 = ((float)(n2 - i2) - f2) * h2;
+    const float x2 = 0.5f * (opx2 - omx2);
+    const float sn = fsqrt(opx2 * omx2);
+    // eq. (3) with x1 = -mx1
+    const float imx1 = frcp(mx1);
+    const float r = 0.5f * (1.f + fsqrt(1.f + 4.f * alpha * mx1 * x2)) * imx1;
+    const float R = r * sn, Z = r * x2;
+    // analytic metric (eqs. 2, 8)
+    const float ir = frcp(r);
+    const float ir3 = ir * ir * ir;
+    const float x1R = sn * (r + 3.f * alpha * x2) * ir3;
+    const float x1Z = (x2 * r + alpha * (3.f * x2 * x2 - 1.f)) * ir3;
+    const float x2R = -x2 * sn * ir;
+    const float x2Z = sn * sn * ir;
+    const float ER = -(x1R * p1 + x2R * p2);
+    const float EZ = -(x1Z * p1 + x2Z * p2);
 
-        // new conforming position from the displacement
-        const float dr2 = 2.f * (R * dX + Z * dZ) + (dX * dX + dY * dY + dZ * dZ);  // r'^2 - r^2
-        const float rn = sqrtf(Rn2 + Zn * Zn);
-        const float dr = dr2 / (rn + r);
-        const float irr = 1.f / (r * rn);
-        const float dx2 = (dZ * r - Z * dr) * irr;
-        const float dx1 = dr * irr - alpha * (dx2 * r * r - x2 * dr * (2.f * r + dr)) * irr * irr;
-        float t1 = f1 + dx1 * ih1;
-        float k1 = floorf(t1);
-        int i1n = i1 + (int)k1;
-        float f1n = t1 - k1;
-        if (f1n >= 1.f) { f1n = 0.f; ++i1n; }
-        float t2 = f2 + dx2 * ih2;
-        float k2 = floorf(t2);
-        int i2n = i2 + (int)k2;
-        float f2n = t2 - k2;
-        if (f2n >= 1.f) { f2n = 0.f; ++i2n; }
-        if (i2n <= 0 || i2n >= n2 - 1) {
-            // next to the axis: distance to it from 1 -+ x2' = R'^2 / (r' (r' +- Z'))
-            if (Zn > 0.f) {
-                const float u = Rn2 / (rn * (rn + Zn)) * ih2;     // (1 - x2') / h2
-                const float j = floorf(u);
-                i2n = n2 - 1 - (int)j;
-                f2n = 1.f - (u - j);
-                if (f2n >= 1.f) { f2n = 0.f; ++i2n; }
-            } else {
-                const float u = Rn2 / (rn * (rn - Zn)) * ih2;     // (1 + x2') / h2
-                const float j = floorf(u);
-                i2n = (int)j;
-                f2n = u - j;
-            }
-            if (i2n < 0) { i2n = 0; f2n = 0.f; }
-            if (i2n > n2 - 1) { i2n = n2 - 1; f2n = 0.99999994f; }
-        }
-
-        // boundaries
-        const float tmid = chord_inside<float>(gp, R, Z, dX, dY, dZ);
-        if (i1n < 0 || tmid > 0.f) {
-            const float t_in = tmid > 0.f ? tmid : 1.f;
-            tally_impact<float>(gp, sp, s, ns, R, Z, dX, dY, dZ, t_in, vR, vZ, vT, tally,
-                                tally_count, 24);
-            cell[p] = DEAD;
-            ++n_abs;
-            continue;
-        }
-        if (i1n >= n1) {
-            cell[p] = DEAD;
-            ++n_esc;
-            continue;
-        }
-        cell[p] = pack_cell(i1n, i2n);
-        f1a[p] = f1n;
-        f2a[p] = f2n;
-        vRa[p] = vRn;
-        vZa[p] = vZ;
-        vTa[p] = vTn;
-        if (dep) {
-            const int o = i2n * nx + i1n;
-            const float a1 = 1.f - f1n, a2 = 1.f - f2n;
-            atomicAdd(&dep[o], a1 * a2);
-            atomicAdd(&dep[o + 1], f1n * a2);
-            atomicAdd(&dep[o + nx], a1 * f2n);
-            atomicAdd(&dep[o + nx + 1], f1n * f2n);
-        }
+    // Boris kick (eq. 9: dV_R = -omega V_Theta dt, dV_Theta = +omega V_R dt).
+    // The rotation is applied as v + ((cos - 1) v + sin v_perp) with cos - 1
+    // held separately, so its FP32 form preserves |v| to ~1e-10 per step
+    // instead of drifting by the rounding of cos.
+    vR += qmh * ER;
+    vZ += qmh * EZ;
+    {
+        const float t = vR + (K.rcm1 * vR - K.rs * vT);
+        vT = vT + (K.rs * vR + K.rcm1 * vT);
+        vR = t;
     }
-    block_count_add(n_live, reinterpret_cast<unsigned long long*>(&ctr->pushed[s]));
-    block_count_add(n_abs, reinterpret_cast<unsigned long long*>(&ctr->absorbed[s]));
-    block_count_add(n_esc, reinterpret_cast<unsigned long long*>(&ctr->escaped[s]));
+    vR += qmh * ER;
+    vZ += qmh * EZ;
+
+    // drift in the local Cartesian frame
+    const float dX = step * vR, dY = step * vT, dZ = step * vZ;
+    const float X = R + dX, Zn = Z + dZ;
+    const float Rn2 = X * X + dY * dY;
+    const float Rn = fsqrt(Rn2);
+    // rotation of (v_R, v_Theta) into the new meridional plane, again as
+    // v + ((cos - 1) v + sin v_perp) with cos - 1 = -dY^2 / (R' (X + R'))
+    float cm = 0.f, sr = 0.f;
+    if (Rn > 0.f) {
+        const float iR = frcp(Rn);
+        sr = dY * iR;
+        cm = X > 0.f ? -(dY * dY) * iR * frcp(X + Rn) : X * iR - 1.f;
+    }
+    const float vRn = vR + (cm * vR + sr * vT);
+    const float vTn = vT + (-sr * vR + cm * vT);
+
+    // new conforming position from the displacement
+    const float dr2 = 2.f * (R * dX + Z * dZ) + (dX * dX + dY * dY + dZ * dZ);  // r'^2 - r^2
+    const float rn = fsqrt(Rn2 + Zn * Zn);
+    const float dr = dr2 * frcp(rn + r);
+    const float irr = frcp(r * rn);
+    const float dx2 = (dZ * r - Z * dr) * irr;
+    const float dx1 = dr * irr - alpha * (dx2 * r * r - x2 * dr * (2.f * r + dr)) * irr * irr;
+    const float t1 = f1 + dx1 * K.ih1;
+    const float k1 = floorf(t1);
+    i1n = i1 + (int)k1;
+    f1n = t1 - k1;
+    if (f1n >= 1.f) { f1n = 0.f; ++i1n; }
+    const float t2 = f2 + dx2 * K.ih2;
+    const float k2 = floorf(t2);
+    i2n = i2 + (int)k2;
+    f2n = t2 - k2;
+    if (f2n >= 1.f) { f2n = 0.f; ++i2n; }
+    if (i2n <= 0 || i2n >= n2 - 1) {
+        // next to the axis: distance to it from 1 -+ x2' = R'^2 / (r' (r' +- Z'))
+        if (Zn > 0.f) {
+            const float u = Rn2 * frcp(rn * (rn + Zn)) * K.ih2;     // (1 - x2') / h2
+            const float j = floorf(u);
+            i2n = n2 - 1 - (int)j;
+            f2n = 1.f - (u - j);
+            if (f2n >= 1.f) { f2n = 0.f; ++i2n; }
+        } else {
+            const float u = Rn2 * frcp(rn * (rn - Zn)) * K.ih2;     // (1 + x2') / h2
+            const float j = floorf(u);
+            i2n = (int)j;
+            f2n = u - j;
+        }
+        if (i2n < 0) { i2n = 0; f2n = 0.f; }
+        if (i2n > n2 - 1) { i2n = n2 - 1; f2n = 0.99999994f; }
+    }
+
+    // boundaries
+    const float tmid = chord_inside<float>(gp, R, Z, dX, dY, dZ);
+    if (i1n < 0 || tmid > 0.f) {
+        const float t_in = tmid > 0.f ? tmid : 1.f;
+        tally_impact<float>(gp, sp, s, ns, R, Z, dX, dY, dZ, t_in, vR, vZ, vT, tally, tally_count, 24);
+        cell[p] = DEAD;
+        return 1;
+    }
+    if (i1n >= n1) {
+        cell[p] = DEAD;
+        return 2;
+    }
+    cell[p] = pack_cell(i1n, i2n);
+    f1a[p] = f1n;
+    f2a[p] = f2n;
+    vRa[p] = vRn;
+    vZa[p] = vZ;
+    vTa[p] = vTn;
+    return 0;
 }
 
 // ----------------------------------------------------------------- FP64 plain push
@@ -310,63 +330,260 @@ __device__ inline int drift_and_bound64(const GrainParams& gp, const SpeciesPara
     return 0;
 }
 
-__global__ void __launch_bounds__(BLOCK)
-k_push_plain(GrainParams gp, SpeciesParams sp, int s, int ns,
-             double* __restrict__ x1a, double* __restrict__ x2a, double* __restrict__ vRa,
-             double* __restrict__ vZa, double* __restrict__ vTa,
-             const double2* __restrict__ grad, double* __restrict__ dep,
-             DevCounters* __restrict__ ctr, double* __restrict__ tally,
-             unsigned long long* __restrict__ tally_count) {
-    const int64_t n = ctr->n[s];
+// One particle of the FP64 plain form; same return convention as the split form.
+__device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams& sp, int s, int ns,
+                                     int64_t p, double* __restrict__ x1a, double* __restrict__ x2a,
+                                     double* __restrict__ vRa, double* __restrict__ vZa,
+                                     double* __restrict__ vTa, const double2* __restrict__ grad,
+                                     double* __restrict__ tally,
+                                     unsigned long long* __restrict__ tally_count, int& i1n,
+                                     int& i2n, double& f1n, double& f2n) {
+    const double x1 = x1a[p];
+    if (x1 > 0.0) return -1;
     const int nx = gp.nx;
     const double alpha = gp.alpha;
-    uint32_t n_live = 0, n_abs = 0, n_esc = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const double x1 = x1a[p];
-        if (x1 > 0.0) continue;
-        ++n_live;
-        const double x2 = x2a[p];
-        double vR = vRa[p], vZ = vZa[p], vT = vTa[p];
-        int i1, i2;
+    const double x2 = x2a[p];
+    double vR = vRa[p], vZ = vZa[p], vT = vTa[p];
+    int i1, i2;
+    double f1, f2;
+    locate64(gp, x1, x2, i1, i2, f1, f2);
+    const int idx = i2 * nx + i1;
+    const double2 g00 = grad[idx], g10 = grad[idx + 1];
+    const double2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
+    const double w00 = (1 - f1) * (1 - f2), w10 = f1 * (1 - f2);
+    const double w01 = (1 - f1) * f2, w11 = f1 * f2;
+    const double p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
+    const double p2 = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
+    const double r = r_of(x1, x2, alpha);
+    const double sn = sqrt(fmax(1.0 - x2 * x2, 0.0));
+    const double R = r * sn, Z = r * x2;
+    const Metric<double> m = metric_at(r, x2, sn, alpha);
+    const double ER = -(m.x1R * p1 + m.x2R * p2);
+    const double EZ = -(m.x1Z * p1 + m.x2Z * p2);
+    vR += sp.qm_half * ER;
+    vZ += sp.qm_half * EZ;
+    {
+        const double t = sp.rot_c * vR - sp.rot_s * vT;
+        vT = sp.rot_s * vR + sp.rot_c * vT;
+        vR = t;
+    }
+    vR += sp.qm_half * ER;
+    vZ += sp.qm_half * EZ;
+    double x1n, x2n, vRn, vTn;
+    const int st = drift_and_bound64(gp, sp, s, ns, R, Z, vR, vZ, vT, gp.step, x1n, x2n, vRn, vTn,
+                                     tally, tally_count);
+    if (st != 0) {
+        x1a[p] = FP64_DEAD;
+        return st;
+    }
+    x1a[p] = x1n;
+    x2a[p] = x2n;
+    vRa[p] = vRn;
+    vZa[p] = vZ;
+    vTa[p] = vTn;
+    locate64(gp, x1n, x2n, i1n, i2n, f1n, f2n);
+    return 0;
+}
+
+// ----------------------------------------------------------------- chunked push kernel
+// A workgroup pushes a chunk of PB * BLOCK consecutive (cell-sorted) particles,
+// then deposits their charge into an LDS window of nodes that covers the
+// chunk's new cells (or, when the chunk is spread too wide, a fixed window
+// around its mean cell; particles outside fall back to global atomics).  The
+// window's non-zero nodes are then added to the global deposit array once per
+// chunk.
+constexpr int PB = 8;
+constexpr int CHUNK = BLOCK * PB;
+constexpr int WIN_CAP = 4096;
+
+__device__ inline void block_reduce7(int v[7], int (*red)[BLOCK / 64]) {
+    // v: min i1, max i1, min i2, max i2, count, sum i1, sum i2
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = min(v[0], __shfl_xor(v[0], o));
+        v[1] = max(v[1], __shfl_xor(v[1], o));
+        v[2] = min(v[2], __shfl_xor(v[2], o));
+        v[3] = max(v[3], __shfl_xor(v[3], o));
+        v[4] += __shfl_xor(v[4], o);
+        v[5] += __shfl_xor(v[5], o);
+        v[6] += __shfl_xor(v[6], o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 7; ++k) red[k][w] = v[k];
+    __syncthreads();
+    for (int k = 0; k < 7; ++k) v[k] = red[k][0];
+    for (int q = 1; q < BLOCK / 64; ++q) {
+        v[0] = min(v[0], red[0][q]);
+        v[1] = max(v[1], red[1][q]);
+        v[2] = min(v[2], red[2][q]);
+        v[3] = max(v[3], red[3][q]);
+        v[4] += red[4][q];
+        v[5] += red[5][q];
+        v[6] += red[6][q];
+    }
+    __syncthreads();
+}
+
+// Deposit window of one chunk: the bounding box of the chunk's current cells
+// widened by WIN_MARGIN cells on every side (clipped to the grid), or, if that
+// exceeds the LDS capacity, a 64-column window around the chunk's mean cell.
+// Particles whose new cell falls outside go straight to global atomics.
+constexpr int WIN_MARGIN = 4;
+
+struct Window {
+    int wi0, wj0, W, H, C;   // first node, extent in nodes, lane-striped copies
+    bool on;
+};
+
+template <bool SPLIT>
+__device__ inline void old_cell(const GrainParams& gp, const PBuf& b, int64_t p, int& i1, int& i2) {
+    if constexpr (SPLIT) {
+        const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
+        if (c < 0) { i1 = -1; return; }
+        i1 = cell_i1(c);
+        i2 = cell_i2(c);
+    } else {
+        const double x1 = static_cast<const double*>(b.pos1)[p];
+        if (x1 > 0.0) { i1 = -1; return; }
         double f1, f2;
-        locate64(gp, x1, x2, i1, i2, f1, f2);
-        const int idx = i2 * nx + i1;
-        const double2 g00 = grad[idx], g10 = grad[idx + 1];
-        const double2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
-        const double w00 = (1 - f1) * (1 - f2), w10 = f1 * (1 - f2);
-        const double w01 = (1 - f1) * f2, w11 = f1 * f2;
-        const double p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
-        const double p2 = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
-        const double r = r_of(x1, x2, alpha);
-        const double sn = sqrt(fmax(1.0 - x2 * x2, 0.0));
-        const double R = r * sn, Z = r * x2;
-        const Metric<double> m = metric_at(r, x2, sn, alpha);
-        const double ER = -(m.x1R * p1 + m.x2R * p2);
-        const double EZ = -(m.x1Z * p1 + m.x2Z * p2);
-        vR += sp.qm_half * ER;
-        vZ += sp.qm_half * EZ;
-        {
-            const double t = sp.rot_c * vR - sp.rot_s * vT;
-            vT = sp.rot_s * vR + sp.rot_c * vT;
-            vR = t;
+        locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
+    }
+}
+
+template <bool SPLIT>
+__device__ inline Window chunk_window(const GrainParams& gp, const PBuf& b, int64_t base, int64_t n,
+                                      int (*red)[BLOCK / 64]) {
+    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
+    for (int k = 0; k < PB; ++k) {
+        const int64_t p = base + k * BLOCK + threadIdx.x;
+        if (p >= n) break;
+        int i1, i2;
+        old_cell<SPLIT>(gp, b, p, i1, i2);
+        if (i1 < 0) continue;
+        v[0] = min(v[0], i1);
+        v[1] = max(v[1], i1);
+        v[2] = min(v[2], i2);
+        v[3] = max(v[3], i2);
+        v[4] += 1;
+        v[5] += i1;
+        v[6] += i2;
+    }
+    block_reduce7(v, red);
+    Window w;
+    w.on = v[4] > 0;
+    if (!w.on) return w;
+    const int nx = gp.nx, ny = gp.n2 + 1;
+    w.wi0 = max(v[0] - WIN_MARGIN, 0);
+    w.wj0 = max(v[2] - WIN_MARGIN, 0);
+    w.W = min(v[1] + WIN_MARGIN + 1, gp.n1) - w.wi0 + 1;
+    w.H = min(v[3] + WIN_MARGIN + 1, gp.n2) - w.wj0 + 1;
+    if (w.W * w.H > WIN_CAP) {
+        w.W = min(w.W, 64);
+        w.H = min(w.H, WIN_CAP / w.W);
+        w.wi0 = max(0, min(v[5] / v[4] - w.W / 2, nx - w.W));
+        w.wj0 = max(0, min(v[6] / v[4] - w.H / 2, ny - w.H));
+    }
+    // Up to 16 lane-striped copies of every window node (copy = lane mod C; the
+    // copies of a node sit in consecutive LDS banks): particles of one wave
+    // landing on the same node add into different words instead of
+    // serialising on one address.
+    w.C = 16;
+    while (w.C > 1 && w.W * w.H * w.C > WIN_CAP) w.C >>= 1;
+    return w;
+}
+
+template <typename T>
+__device__ inline void deposit_one(const GrainParams& gp, const Window& w, T* __restrict__ win,
+                                   T* __restrict__ dep, int i1, int i2, T f1, T f2) {
+    const T a1 = T(1) - f1, a2 = T(1) - f2;
+    const T w00 = a1 * a2, w10 = f1 * a2, w01 = a1 * f2, w11 = f1 * f2;
+    const int li = i1 - w.wi0, lj = i2 - w.wj0;
+    if (li >= 0 && li < w.W - 1 && lj >= 0 && lj < w.H - 1) {
+        const int C = w.C, cp = threadIdx.x & (C - 1);
+        const int o = lj * w.W + li;
+        atomicAdd(&win[o * C + cp], w00);
+        atomicAdd(&win[(o + 1) * C + cp], w10);
+        atomicAdd(&win[(o + w.W) * C + cp], w01);
+        atomicAdd(&win[(o + w.W + 1) * C + cp], w11);
+    } else {
+        const int nx = gp.nx;
+        const int o = i2 * nx + i1;
+        atomicAdd(&dep[o], w00);
+        atomicAdd(&dep[o + 1], w10);
+        atomicAdd(&dep[o + nx], w01);
+        atomicAdd(&dep[o + nx + 1], w11);
+    }
+}
+
+template <typename T>
+__device__ inline void flush_window(const GrainParams& gp, const Window& w, T* __restrict__ win,
+                                    T* __restrict__ dep) {
+    const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
+    for (int q = threadIdx.x; q < nodes_w; q += BLOCK) {
+        T val = T(0);
+        for (int c = 0; c < C; ++c) {
+            const int a = q * C + ((c + q) & (C - 1));
+            val += win[a];
+            win[a] = T(0);
         }
-        vR += sp.qm_half * ER;
-        vZ += sp.qm_half * EZ;
-        double x1n, x2n, vRn, vTn;
-        const int st = drift_and_bound64(gp, sp, s, ns, R, Z, vR, vZ, vT, gp.step, x1n, x2n, vRn,
-                                         vTn, tally, tally_count);
-        if (st != 0) {
-            x1a[p] = FP64_DEAD;
-            if (st == 1) ++n_abs; else ++n_esc;
-            continue;
+        if (val != T(0)) {
+            const int row = q / w.W;
+            atomicAdd(&dep[(w.wj0 + row) * nx + w.wi0 + (q - row * w.W)], val);
         }
-        x1a[p] = x1n;
-        x2a[p] = x2n;
-        vRa[p] = vRn;
-        vZa[p] = vZ;
-        vTa[p] = vTn;
-        if (dep) deposit64(gp, dep, x1n, x2n);
+    }
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(BLOCK)
+k_push(GrainParams gp, SpeciesParams sp, int s, int ns, PBuf b, const void* __restrict__ grad,
+       void* __restrict__ dep_v, DevCounters* __restrict__ ctr, double* __restrict__ tally,
+       unsigned long long* __restrict__ tally_count) {
+    using T = typename std::conditional<SPLIT, float, double>::type;
+    __shared__ T win[WIN_CAP];
+    __shared__ int red[7][BLOCK / 64];
+    T* dep = static_cast<T*>(dep_v);
+    const int64_t n = ctr->n[s];
+    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = T(0);
+    __syncthreads();
+    SplitConsts K;
+    if constexpr (SPLIT) K = split_consts(gp, sp);
+    uint32_t n_live = 0, n_abs = 0, n_esc = 0;
+    for (int64_t chunk = blockIdx.x; chunk * CHUNK < n; chunk += gridDim.x) {
+        const int64_t base = chunk * CHUNK;
+        Window w;
+        w.on = false;
+        if (dep) w = chunk_window<SPLIT>(gp, b, base, n, red);
+#pragma unroll 1
+        for (int k = 0; k < PB; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            if (p >= n) break;
+            int a, c;
+            T f, g;
+            int st;
+            if constexpr (SPLIT)
+                st = push_split_one(gp, sp, K, s, ns, p, static_cast<int32_t*>(b.pos0),
+                                    static_cast<float*>(b.pos1), static_cast<float*>(b.pos2),
+                                    static_cast<float*>(b.vR), static_cast<float*>(b.vZ),
+                                    static_cast<float*>(b.vT), static_cast<const float2*>(grad),
+                                    tally, tally_count, a, c, f, g);
+            else
+                st = push_plain_one(gp, sp, s, ns, p, static_cast<double*>(b.pos1),
+                                    static_cast<double*>(b.pos2), static_cast<double*>(b.vR),
+                                    static_cast<double*>(b.vZ), static_cast<double*>(b.vT),
+                                    static_cast<const double2*>(grad), tally, tally_count, a, c, f,
+                                    g);
+            if (st < 0) continue;
+            ++n_live;
+            if (st == 1) { ++n_abs; continue; }
+            if (st == 2) { ++n_esc; continue; }
+            if (w.on) deposit_one<T>(gp, w, win, dep, a, c, f, g);
+        }
+        if (w.on) {
+            __syncthreads();
+            flush_window<T>(gp, w, win, dep);
+            __syncthreads();
+        }
     }
     block_count_add(n_live, reinterpret_cast<unsigned long long*>(&ctr->pushed[s]));
     block_count_add(n_abs, reinterpret_cast<unsigned long long*>(&ctr->absorbed[s]));
@@ -374,35 +591,44 @@ k_push_plain(GrainParams gp, SpeciesParams sp, int s, int ns,
 }
 
 // ----------------------------------------------------------------- deposit only
+// Deposit of the current particles (initial field, standalone solves) with the
+// same chunk windows as the push.
+template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_deposit_split(GrainParams gp, int s, const int32_t* __restrict__ cell,
-                const float* __restrict__ f1a, const float* __restrict__ f2a,
-                float* __restrict__ dep, const DevCounters* __restrict__ ctr) {
+k_deposit(GrainParams gp, int s, PBuf b, void* __restrict__ dep_v, const DevCounters* __restrict__ ctr) {
+    using T = typename std::conditional<SPLIT, float, double>::type;
+    __shared__ T win[WIN_CAP];
+    __shared__ int red[7][BLOCK / 64];
+    T* dep = static_cast<T*>(dep_v);
     const int64_t n = ctr->n[s];
-    const int nx = gp.nx;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = cell[p];
-        if (c < 0) continue;
-        const int o = cell_i2(c) * nx + cell_i1(c);
-        const float f1 = f1a[p], f2 = f2a[p];
-        atomicAdd(&dep[o], (1.f - f1) * (1.f - f2));
-        atomicAdd(&dep[o + 1], f1 * (1.f - f2));
-        atomicAdd(&dep[o + nx], (1.f - f1) * f2);
-        atomicAdd(&dep[o + nx + 1], f1 * f2);
-    }
-}
-
-__global__ void __launch_bounds__(BLOCK)
-k_deposit_plain(GrainParams gp, int s, const double* __restrict__ x1a,
-                const double* __restrict__ x2a, double* __restrict__ dep,
-                const DevCounters* __restrict__ ctr) {
-    const int64_t n = ctr->n[s];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const double x1 = x1a[p];
-        if (x1 > 0.0) continue;
-        deposit64(gp, dep, x1, x2a[p]);
+    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = T(0);
+    __syncthreads();
+    for (int64_t chunk = blockIdx.x; chunk * CHUNK < n; chunk += gridDim.x) {
+        const int64_t base = chunk * CHUNK;
+        const Window w = chunk_window<SPLIT>(gp, b, base, n, red);
+        if (!w.on) continue;
+        for (int k = 0; k < PB; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            if (p >= n) break;
+            int i1, i2;
+            T f1, f2;
+            if constexpr (SPLIT) {
+                const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
+                if (c < 0) continue;
+                i1 = cell_i1(c);
+                i2 = cell_i2(c);
+                f1 = static_cast<const float*>(b.pos1)[p];
+                f2 = static_cast<const float*>(b.pos2)[p];
+            } else {
+                const double x1 = static_cast<const double*>(b.pos1)[p];
+                if (x1 > 0.0) continue;
+                locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
+            }
+            deposit_one<T>(gp, w, win, dep, i1, i2, f1, f2);
+        }
+        __syncthreads();
+        flush_window<T>(gp, w, win, dep);
+        __syncthreads();
     }
 }
 
@@ -613,39 +839,94 @@ k_readback(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restr
     }
 }
 
-// ----------------------------------------------------------------- counting sort
-__device__ inline int sort_key(const GrainParams& gp, bool split, const PBuf& b, int64_t p,
-                               int ncells) {
+// ----------------------------------------------------------------- tile sort
+// Particles are ordered by tiles of 2^tile_log2 x 2^tile_log2 cells (tiles in
+// row-major order, x1 fastest); inside a tile the order is arbitrary.  That is
+// all the push needs: a chunk of consecutive particles then covers one tile (or
+// a few), so its deposit window and its field nodes stay small.  The sort is a
+// one-pass counting sort without global atomics: each of SORT_BLOCKS blocks
+// takes a contiguous slot range, builds the histogram of its tiles in LDS,
+// the histograms are scanned tile-major, and each block scatters its
+// particles to its own offsets.  Dead slots are dropped on the way.
+constexpr int SORT_BLOCKS = 1024;
+
+__device__ inline int tile_key(const GrainParams& gp, bool split, const PBuf& b, int64_t p) {
+    int i1, i2;
     if (split) {
         const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
-        return c < 0 ? ncells : cell_i2(c) * gp.n1 + cell_i1(c);
+        if (c < 0) return -1;
+        i1 = cell_i1(c);
+        i2 = cell_i2(c);
+    } else {
+        const double x1 = static_cast<const double*>(b.pos1)[p];
+        if (x1 > 0.0) return -1;
+        double f1, f2;
+        locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
     }
-    const double x1 = static_cast<const double*>(b.pos1)[p];
-    if (x1 > 0.0) return ncells;
-    int i1, i2;
-    double f1, f2;
-    locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
-    return i2 * gp.n1 + i1;
+    return (i2 >> gp.tile_log2) * gp.ntx + (i1 >> gp.tile_log2);
+}
+
+// Run-length segments of equal keys inside a wave (all 64 lanes active): the
+// first lane of each run is its head; head_lane and, for heads, the run length.
+__device__ inline void wave_runs(int key, int& head_lane, int& run_len, bool& is_head) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1);
+    is_head = (lane == 0) || (key != prev);
+    const unsigned long long hm = __ballot(is_head);
+    const unsigned long long le = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1);
+    head_lane = 63 - __clzll((long long)(hm & le));
+    const unsigned long long gt = hm & ~le;
+    run_len = (gt ? (__ffsll((long long)gt) - 1) : 64) - lane;
+}
+
+__device__ inline void sort_range(const DevCounters* ctr, int s, int64_t& lo, int64_t& hi) {
+    const int64_t n = ctr->n[s];
+    const int64_t per = (n + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    lo = min<int64_t>((int64_t)blockIdx.x * per, n);
+    hi = min<int64_t>(lo + per, n);
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_sort_hist(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
-            int* __restrict__ count, int ncells) {
-    const int64_t n = ctr->n[s];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&count[sort_key(gp, split, b, p, ncells)], 1);
+k_tile_hist(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
+            int* __restrict__ hist) {
+    extern __shared__ int lh[];
+    const int nt = gp.ntiles;
+    for (int t = threadIdx.x; t < nt; t += BLOCK) lh[t] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    sort_range(ctr, s, lo, hi);
+    for (int64_t base = lo; base < hi; base += BLOCK) {
+        const int64_t p = base + threadIdx.x;
+        const int key = p < hi ? tile_key(gp, split, b, p) : -1;
+        int head, len;
+        bool is_head;
+        wave_runs(key, head, len, is_head);
+        if (is_head && key >= 0) atomicAdd(&lh[key], len);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += BLOCK) hist[(size_t)t * SORT_BLOCKS + blockIdx.x] = lh[t];
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_sort_scatter(GrainParams gp, int s, bool split, PBuf src, PBuf dst,
-               const DevCounters* __restrict__ ctr, int* __restrict__ cursor, int ncells) {
-    const int64_t n = ctr->n[s];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int key = sort_key(gp, split, src, p, ncells);
-        if (key == ncells) continue;
-        const int64_t o = atomicAdd(&cursor[key], 1);
+k_tile_scatter(GrainParams gp, int s, bool split, PBuf src, PBuf dst,
+               const DevCounters* __restrict__ ctr, const int* __restrict__ offset) {
+    extern __shared__ int cur[];
+    const int nt = gp.ntiles;
+    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = offset[(size_t)t * SORT_BLOCKS + blockIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    int64_t lo, hi;
+    sort_range(ctr, s, lo, hi);
+    for (int64_t base = lo; base < hi; base += BLOCK) {
+        const int64_t p = base + threadIdx.x;
+        const int key = p < hi ? tile_key(gp, split, src, p) : -1;
+        int head, len;
+        bool is_head;
+        wave_runs(key, head, len, is_head);
+        int start = 0;
+        if (is_head && key >= 0) start = atomicAdd(&cur[key], len);
+        const int64_t o = (int64_t)__shfl(start, head) + (lane - head);
+        if (key < 0) continue;
         if (split) {
             static_cast<int32_t*>(dst.pos0)[o] = static_cast<const int32_t*>(src.pos0)[p];
             static_cast<float*>(dst.pos1)[o] = static_cast<const float*>(src.pos1)[p];
@@ -664,8 +945,8 @@ k_sort_scatter(GrainParams gp, int s, bool split, PBuf src, PBuf dst,
     }
 }
 
-__global__ void k_sort_live(DevCounters* ctr, int s, const int* offset, int ncells) {
-    ctr->n_sorted[s] = offset[ncells];
+__global__ void k_sort_live(DevCounters* ctr, int s, const int* offset, int total_index) {
+    ctr->n_sorted[s] = offset[total_index];
 }
 
 __global__ void k_sort_commit(DevCounters* ctr, int s) { ctr->n[s] = ctr->n_sorted[s]; }
@@ -681,37 +962,29 @@ static bool is_split(apic_ctx* ctx) { return ctx->opts.precision == APIC_FP32_SP
 
 hipError_t launch_push(apic_ctx* ctx, Grain& g, int s) {
     const PBuf& b = g.buf[s][g.cur[s]];
-    const int grid = grid_for(ctx, g.host_slots[s]);
+    const int64_t chunks = (g.host_slots[s] + CHUNK - 1) / CHUNK;
+    const int64_t cap = (int64_t)ctx->num_cus * 8;
+    const int grid = (int)std::max<int64_t>(1, std::min(chunks, cap));
     void* dep = ctx->opts.frozen_field ? nullptr : g.dep[s];
-    if (is_split(ctx)) {
-        hipLaunchKernelGGL(k_push_split, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
-                           g.ns, static_cast<int32_t*>(b.pos0), static_cast<float*>(b.pos1),
-                           static_cast<float*>(b.pos2), static_cast<float*>(b.vR),
-                           static_cast<float*>(b.vZ), static_cast<float*>(b.vT),
-                           static_cast<const float2*>(g.grad), static_cast<float*>(dep), g.ctr,
-                           g.tally, g.tally_count);
-    } else {
-        hipLaunchKernelGGL(k_push_plain, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
-                           g.ns, static_cast<double*>(b.pos1), static_cast<double*>(b.pos2),
-                           static_cast<double*>(b.vR), static_cast<double*>(b.vZ),
-                           static_cast<double*>(b.vT), static_cast<const double2*>(g.grad),
-                           static_cast<double*>(dep), g.ctr, g.tally, g.tally_count);
-    }
+    if (is_split(ctx))
+        hipLaunchKernelGGL(k_push<true>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
+                           g.ns, b, g.grad, dep, g.ctr, g.tally, g.tally_count);
+    else
+        hipLaunchKernelGGL(k_push<false>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
+                           g.ns, b, g.grad, dep, g.ctr, g.tally, g.tally_count);
     return hipGetLastError();
 }
 
 hipError_t launch_deposit_all(apic_ctx* ctx, Grain& g, int s) {
     const PBuf& b = g.buf[s][g.cur[s]];
-    const int grid = grid_for(ctx, g.host_slots[s]);
+    const int64_t chunks = (g.host_slots[s] + CHUNK - 1) / CHUNK;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)ctx->num_cus * 8));
     if (is_split(ctx))
-        hipLaunchKernelGGL(k_deposit_split, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s,
-                           static_cast<const int32_t*>(b.pos0), static_cast<const float*>(b.pos1),
-                           static_cast<const float*>(b.pos2), static_cast<float*>(g.dep[s]),
-                           g.ctr);
+        hipLaunchKernelGGL(k_deposit<true>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s, b,
+                           g.dep[s], g.ctr);
     else
-        hipLaunchKernelGGL(k_deposit_plain, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s,
-                           static_cast<const double*>(b.pos1), static_cast<const double*>(b.pos2),
-                           static_cast<double*>(g.dep[s]), g.ctr);
+        hipLaunchKernelGGL(k_deposit<false>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s, b,
+                           g.dep[s], g.ctr);
     return hipGetLastError();
 }
 
@@ -761,27 +1034,28 @@ hipError_t launch_readback(apic_ctx* ctx, Grain& g, int s, int64_t n, double* dx
 }
 
 hipError_t launch_sort(apic_ctx* ctx, Grain& g, int s) {
-    const int nc = g.ncells;
     const PBuf& src = g.buf[s][g.cur[s]];
     const PBuf& dst = g.buf[s][1 - g.cur[s]];
-    const int grid = grid_for(ctx, g.host_slots[s]);
-    hipError_t e = launch_fill(ctx, g.sort_count, sizeof(int) * (size_t)(nc + 1));
+    const size_t lds = sizeof(int) * (size_t)g.gp.ntiles;
+    const int total = g.gp.ntiles * SORT_BLOCKS;
+    hipLaunchKernelGGL(k_tile_hist, dim3(SORT_BLOCKS), dim3(BLOCK), lds, ctx->stream, g.gp, s,
+                       is_split(ctx), src, g.ctr, g.sort_count);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s, is_split(ctx),
-                       src, g.ctr, g.sort_count, nc);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     size_t bytes = g.scan_tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(g.scan_tmp, bytes, g.sort_count, g.sort_offset, nc + 1,
+    e = hipcub::DeviceScan::ExclusiveSum(g.scan_tmp, bytes, g.sort_count, g.sort_offset, total + 1,
                                          ctx->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_live, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s, g.sort_offset, nc);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s,
-                       is_split(ctx), src, dst, g.ctr, g.sort_offset, nc);
+    hipLaunchKernelGGL(k_sort_live, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s, g.sort_offset, total);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(SORT_BLOCKS), dim3(BLOCK), lds, ctx->stream, g.gp, s,
+                       is_split(ctx), src, dst, g.ctr, g.sort_offset);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s);
     g.cur[s] = 1 - g.cur[s];
     return hipGetLastError();
 }
+
+int sort_blocks() { return SORT_BLOCKS; }
 
 size_t scan_temp_bytes(int n) {
     size_t bytes = 0;
