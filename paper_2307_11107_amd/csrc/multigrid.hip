@@ -15,29 +15,41 @@ namespace apic {
 
 constexpr int MG_BLOCK = 256;
 
+// FP64 reciprocal: hardware estimate refined by two Newton steps (correct to
+// about 1 ulp); replaces the much longer division sequence in the line solves.
+__device__ inline double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
 // Parallel cyclic reduction on a set of tridiagonal systems held in LDS (a:
 // sub, b: diagonal, c: super, d: rhs).  Equation e belongs to system e / L and
 // couples only inside its system; a[first] = c[last] = 0.  Each thread owns up
 // to K equations.  On return d[e] / b[e] is the solution.
-template <int K>
+template <int K, int NT>
 __device__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int total) {
+    int jj[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) jj[k] = (threadIdx.x + k * NT) % L;
     for (int s = 1; s < L; s <<= 1) {
         double na[K], nb[K], nc[K], nd[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = threadIdx.x + k * MG_BLOCK;
+            const int e = threadIdx.x + k * NT;
             if (e < total) {
-                const int j = e % L;
+                const int j = jj[k];
                 double ai = a[e], bi = b[e], ci = c[e], di = d[e];
                 double an = 0.0, cn = 0.0;
                 if (j - s >= 0) {
-                    const double m = ai / b[e - s];
+                    const double m = ai * rcp64(b[e - s]);
                     bi -= m * c[e - s];
                     di -= m * d[e - s];
                     an = -m * a[e - s];
                 }
                 if (j + s < L) {
-                    const double m = ci / b[e + s];
+                    const double m = ci * rcp64(b[e + s]);
                     bi -= m * a[e + s];
                     di -= m * d[e + s];
                     cn = -m * c[e + s];
@@ -51,7 +63,7 @@ __device__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = threadIdx.x + k * MG_BLOCK;
+            const int e = threadIdx.x + k * NT;
             if (e < total) {
                 a[e] = na[k];
                 b[e] = nb[k];
@@ -96,8 +108,8 @@ __device__ inline double apply_A(const StencilPtrs& p, const double* __restrict_
 }
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
-template <int K>
-__global__ void __launch_bounds__(MG_BLOCK)
+template <int K, int NT>
+__global__ void __launch_bounds__(NT)
 k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
            const double* __restrict__ nn, const double* __restrict__ ss, double* __restrict__ u,
            const double* __restrict__ f) {
@@ -111,7 +123,7 @@ k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
     if (j > n2) return;
     const int nx = n1 + 1;
     const StencilPtrs p = stencil_ptrs(st, nodes);
-    for (int k = threadIdx.x; k < L; k += MG_BLOCK) {
+    for (int k = threadIdx.x; k < L; k += NT) {
         const int i = k + 1;
         const size_t o = (size_t)j * nx + i;
         double rhs = f[o];
@@ -128,8 +140,8 @@ k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
         d[k] = rhs;
     }
     __syncthreads();
-    pcr_solve<K>(a, b, c, d, L, L);
-    for (int k = threadIdx.x; k < L; k += MG_BLOCK) u[(size_t)j * nx + k + 1] = d[k] / b[k];
+    pcr_solve<K, NT>(a, b, c, d, L, L);
+    for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * rcp64(b[k]);
 }
 
 // Relaxation of LPB lines i1 = i (i = 1 + color, 3 + color, ...) per workgroup:
@@ -137,8 +149,8 @@ k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
 // that the row-wise loads stay within a cache line.  On the finest level the
 // axis rows carry a second-neighbour coupling (one-sided d/dx2); it is
 // eliminated with the adjacent row so each line stays tridiagonal.
-template <int K, int LPB>
-__global__ void __launch_bounds__(MG_BLOCK)
+template <int K, int LPB, int NT>
+__global__ void __launch_bounds__(NT)
 k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
            const double* __restrict__ nn, const double* __restrict__ ss, double* __restrict__ u,
            const double* __restrict__ f) {
@@ -153,7 +165,7 @@ k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
     if (i0 > n1 - 1) return;
     const int nx = n1 + 1;
     const StencilPtrs p = stencil_ptrs(st, nodes);
-    for (int q = threadIdx.x; q < total; q += MG_BLOCK) {
+    for (int q = threadIdx.x; q < total; q += NT) {
         const int m = q % LPB, j = q / LPB;
         const int i = i0 + 2 * m;
         const int e = m * L + j;
@@ -195,13 +207,13 @@ k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
         }
     }
     __syncthreads();
-    pcr_solve<K>(a, b, c, d, L, total);
-    for (int q = threadIdx.x; q < total; q += MG_BLOCK) {
+    pcr_solve<K, NT>(a, b, c, d, L, total);
+    for (int q = threadIdx.x; q < total; q += NT) {
         const int m = q % LPB, j = q / LPB;
         const int i = i0 + 2 * m;
         if (i > n1 - 1) continue;
         const int e = m * L + j;
-        u[(size_t)j * nx + i] = d[e] / b[e];
+        u[(size_t)j * nx + i] = d[e] * rcp64(b[e]);
     }
 }
 
@@ -323,44 +335,50 @@ k_coarse_solve(int m, const double* __restrict__ inv, const double* __restrict__
     if (lane == 0) u[row] = acc;
 }
 
-template <int K>
-static void relax_x1(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+// Line-solve launches.  A line of L unknowns gets NT = 512 threads when it is
+// long (fewer equations per thread, shorter PCR critical path), else 256; the
+// x2 sweeps group LPB neighbouring lines of one colour per workgroup while
+// that still leaves at least two workgroups per compute unit.
+template <int K, int NT>
+static void relax_x1_launch(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
     const size_t lds = 4 * sizeof(double) * (size_t)(L.n1 - 1);
     const int lines = (L.n2 + 1 - color + 1) / 2;
-    hipLaunchKernelGGL(k_relax_x1<K>, dim3(lines), dim3(MG_BLOCK), lds, ctx->stream, L.n1, L.n2,
+    hipLaunchKernelGGL((k_relax_x1<K, NT>), dim3(lines), dim3(NT), lds, ctx->stream, L.n1, L.n2,
                        color, L.st, L.nodes, nn, ss, L.u, L.f);
 }
 
-template <int K, int LPB>
-static void relax_x2(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+template <int K, int LPB, int NT>
+static void relax_x2_launch(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
     const size_t lds = 4 * sizeof(double) * (size_t)LPB * (L.n2 + 1);
     const int lines = (L.n1 - 1 - color + 1) / 2;
     if (lines <= 0) return;
     const int blocks = (lines + LPB - 1) / LPB;
-    hipLaunchKernelGGL((k_relax_x2<K, LPB>), dim3(blocks), dim3(MG_BLOCK), lds, ctx->stream, L.n1,
+    hipLaunchKernelGGL((k_relax_x2<K, LPB, NT>), dim3(blocks), dim3(NT), lds, ctx->stream, L.n1,
                        L.n2, color, L.st, L.nodes, nn, ss, L.u, L.f);
 }
 
-// Lines of one colour per workgroup for the x2 sweeps: as many as fit in 64 KB
-// of LDS (four FP64 arrays per line) and in eight equations per thread.
-static int x2_lines_per_block(int L) {
-    if (16 * 8 * (size_t)L <= 65536 && 4 * L <= 8 * MG_BLOCK) return 4;
-    if (8 * 8 * (size_t)L <= 65536 && 2 * L <= 8 * MG_BLOCK) return 2;
-    return 1;
-}
-
-static int pcr_k(int total) {
-    const int k = (total + MG_BLOCK - 1) / MG_BLOCK;
+static int pcr_k(int total, int nt) {
+    const int k = (total + nt - 1) / nt;
     return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8;
 }
 
-template <int LPB>
+template <int NT>
+static void relax_x1_k(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
+    switch (pcr_k(L.n1 - 1, NT)) {
+        case 1: relax_x1_launch<1, NT>(ctx, L, nn, ss, color); break;
+        case 2: relax_x1_launch<2, NT>(ctx, L, nn, ss, color); break;
+        case 4: relax_x1_launch<4, NT>(ctx, L, nn, ss, color); break;
+        default: relax_x1_launch<8, NT>(ctx, L, nn, ss, color); break;
+    }
+}
+
+template <int LPB, int NT>
 static void relax_x2_k(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
-    switch (pcr_k(LPB * (L.n2 + 1))) {
-        case 1: relax_x2<1, LPB>(ctx, L, nn, ss, color); break;
-        case 2: relax_x2<2, LPB>(ctx, L, nn, ss, color); break;
-        case 4: relax_x2<4, LPB>(ctx, L, nn, ss, color); break;
-        default: relax_x2<8, LPB>(ctx, L, nn, ss, color); break;
+    switch (pcr_k(LPB * (L.n2 + 1), NT)) {
+        case 1: relax_x2_launch<1, LPB, NT>(ctx, L, nn, ss, color); break;
+        case 2: relax_x2_launch<2, LPB, NT>(ctx, L, nn, ss, color); break;
+        case 4: relax_x2_launch<4, LPB, NT>(ctx, L, nn, ss, color); break;
+        default: relax_x2_launch<8, LPB, NT>(ctx, L, nn, ss, color); break;
     }
 }
 
@@ -369,18 +387,20 @@ static void relax(apic_ctx* ctx, Grain& g, int l) {
     const double* nn = l == 0 ? g.axis_nn : nullptr;
     const double* ss = l == 0 ? g.axis_ss : nullptr;
     for (int color = 0; color < 2; ++color) {
-        switch (pcr_k(L.n1 - 1)) {
-            case 1: relax_x1<1>(ctx, L, nn, ss, color); break;
-            case 2: relax_x1<2>(ctx, L, nn, ss, color); break;
-            case 4: relax_x1<4>(ctx, L, nn, ss, color); break;
-            default: relax_x1<8>(ctx, L, nn, ss, color); break;
-        }
+        if (L.n1 - 1 > 512) relax_x1_k<512>(ctx, L, nn, ss, color);
+        else relax_x1_k<256>(ctx, L, nn, ss, color);
     }
-    const int lpb = x2_lines_per_block(L.n2 + 1);
+    const int Lx2 = L.n2 + 1;
+    const int lines = (L.n1 - 1 + 1) / 2;
+    int lpb = 4;
+    while (lpb > 1 && (4 * sizeof(double) * (size_t)lpb * Lx2 > 65536 || lpb * Lx2 > 8 * 256 ||
+                       (lines + lpb - 1) / lpb < 2 * ctx->num_cus))
+        lpb >>= 1;
     for (int color = 0; color < 2; ++color) {
-        if (lpb == 4) relax_x2_k<4>(ctx, L, nn, ss, color);
-        else if (lpb == 2) relax_x2_k<2>(ctx, L, nn, ss, color);
-        else relax_x2_k<1>(ctx, L, nn, ss, color);
+        if (lpb == 4) relax_x2_k<4, 256>(ctx, L, nn, ss, color);
+        else if (lpb == 2) relax_x2_k<2, 256>(ctx, L, nn, ss, color);
+        else if (Lx2 > 512) relax_x2_k<1, 512>(ctx, L, nn, ss, color);
+        else relax_x2_k<1, 256>(ctx, L, nn, ss, color);
     }
 }
 

@@ -495,7 +495,7 @@ __device__ inline Window chunk_window(const GrainParams& gp, const PBuf& b, int6
 
 template <typename T>
 __device__ inline void deposit_one(const GrainParams& gp, const Window& w, T* __restrict__ win,
-                                   T* __restrict__ dep, int i1, int i2, T f1, T f2) {
+                                   T* __restrict__ dep, int i1, int i2, T f1, T f2) {  // FP64 form
     const T a1 = T(1) - f1, a2 = T(1) - f2;
     const T w00 = a1 * a2, w10 = f1 * a2, w01 = a1 * f2, w11 = f1 * f2;
     const int li = i1 - w.wi0, lj = i2 - w.wj0;
@@ -534,17 +534,68 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w, T* _
     }
 }
 
+// FP32 split form: the window holds 64-bit words of two 32-bit fixed-point
+// sums, the left and the right node of a cell edge (word o = nodes o, o + 1).
+// A particle then needs two integer LDS atomics (bottom and top edge of its
+// cell) instead of four float ones, and the window sums do not depend on the
+// order of the additions.  With C copies a copy receives at most CHUNK / C
+// particles, which sets the fraction bits: 20 + log2(C) (2^-20 .. 2^-24).
+__device__ inline int fx_bits(int C) { return 20 + (31 - __clz(C)); }
+
+__device__ inline void deposit_one(const GrainParams& gp, const Window& w,
+                                   unsigned long long* __restrict__ win, float* __restrict__ dep,
+                                   int i1, int i2, float f1, float f2) {
+    const float a1 = 1.f - f1, a2 = 1.f - f2;
+    const float w00 = a1 * a2, w10 = f1 * a2, w01 = a1 * f2, w11 = f1 * f2;
+    const int li = i1 - w.wi0, lj = i2 - w.wj0;
+    if (li >= 0 && li < w.W - 1 && lj >= 0 && lj < w.H - 1) {
+        const int C = w.C, cp = threadIdx.x & (C - 1);
+        const float sc = (float)(1 << fx_bits(C));
+        const unsigned long long bot =
+            (unsigned long long)(uint32_t)(w00 * sc + 0.5f) | ((unsigned long long)(uint32_t)(w10 * sc + 0.5f) << 32);
+        const unsigned long long top =
+            (unsigned long long)(uint32_t)(w01 * sc + 0.5f) | ((unsigned long long)(uint32_t)(w11 * sc + 0.5f) << 32);
+        const int o = lj * w.W + li;
+        atomicAdd(&win[o * C + cp], bot);
+        atomicAdd(&win[(o + w.W) * C + cp], top);
+    } else {
+        const int nx = gp.nx;
+        const int o = i2 * nx + i1;
+        atomicAdd(&dep[o], w00);
+        atomicAdd(&dep[o + 1], w10);
+        atomicAdd(&dep[o + nx], w01);
+        atomicAdd(&dep[o + nx + 1], w11);
+    }
+}
+
+__device__ inline void flush_window(const GrainParams& gp, const Window& w,
+                                    unsigned long long* __restrict__ win, float* __restrict__ dep) {
+    const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
+    const double isc = 1.0 / (double)(1 << fx_bits(C));
+    for (int q = threadIdx.x; q < nodes_w; q += BLOCK) {
+        const int row = q / w.W, col = q - row * w.W;
+        unsigned long long sum = 0;
+        for (int c = 0; c < C; ++c) sum += win[q * C + ((c + q) & (C - 1))] & 0xFFFFFFFFull;
+        if (col > 0)
+            for (int c = 0; c < C; ++c) sum += win[(q - 1) * C + ((c + q) & (C - 1))] >> 32;
+        if (sum) atomicAdd(&dep[(w.wj0 + row) * nx + w.wi0 + col], (float)((double)sum * isc));
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nodes_w * C; q += BLOCK) win[q] = 0ull;
+}
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
 k_push(GrainParams gp, SpeciesParams sp, int s, int ns, PBuf b, const void* __restrict__ grad,
        void* __restrict__ dep_v, DevCounters* __restrict__ ctr, double* __restrict__ tally,
        unsigned long long* __restrict__ tally_count) {
     using T = typename std::conditional<SPLIT, float, double>::type;
-    __shared__ T win[WIN_CAP];
+    using A = typename std::conditional<SPLIT, unsigned long long, double>::type;
+    __shared__ A win[WIN_CAP];
     __shared__ int red[7][BLOCK / 64];
     T* dep = static_cast<T*>(dep_v);
     const int64_t n = ctr->n[s];
-    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = T(0);
+    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
     __syncthreads();
     SplitConsts K;
     if constexpr (SPLIT) K = split_consts(gp, sp);
@@ -577,11 +628,11 @@ k_push(GrainParams gp, SpeciesParams sp, int s, int ns, PBuf b, const void* __re
             ++n_live;
             if (st == 1) { ++n_abs; continue; }
             if (st == 2) { ++n_esc; continue; }
-            if (w.on) deposit_one<T>(gp, w, win, dep, a, c, f, g);
+            if (w.on) deposit_one(gp, w, win, dep, a, c, f, g);
         }
         if (w.on) {
             __syncthreads();
-            flush_window<T>(gp, w, win, dep);
+            flush_window(gp, w, win, dep);
             __syncthreads();
         }
     }
@@ -597,11 +648,12 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
 k_deposit(GrainParams gp, int s, PBuf b, void* __restrict__ dep_v, const DevCounters* __restrict__ ctr) {
     using T = typename std::conditional<SPLIT, float, double>::type;
-    __shared__ T win[WIN_CAP];
+    using A = typename std::conditional<SPLIT, unsigned long long, double>::type;
+    __shared__ A win[WIN_CAP];
     __shared__ int red[7][BLOCK / 64];
     T* dep = static_cast<T*>(dep_v);
     const int64_t n = ctr->n[s];
-    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = T(0);
+    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
     __syncthreads();
     for (int64_t chunk = blockIdx.x; chunk * CHUNK < n; chunk += gridDim.x) {
         const int64_t base = chunk * CHUNK;
@@ -624,10 +676,10 @@ k_deposit(GrainParams gp, int s, PBuf b, void* __restrict__ dep_v, const DevCoun
                 if (x1 > 0.0) continue;
                 locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
             }
-            deposit_one<T>(gp, w, win, dep, i1, i2, f1, f2);
+            deposit_one(gp, w, win, dep, i1, i2, f1, f2);
         }
         __syncthreads();
-        flush_window<T>(gp, w, win, dep);
+        flush_window(gp, w, win, dep);
         __syncthreads();
     }
 }
