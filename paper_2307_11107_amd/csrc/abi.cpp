@@ -100,12 +100,13 @@ struct Timer {
 };
 
 // ---------------------------------------------------------------- Poisson driver
-int read_norms(apic_ctx* ctx, Grain& g, double* r2, double* b2) {
-    double h[2];
-    HIPCHK(ctx, hipMemcpyAsync(h, &g.ctr->norm2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+int read_norms(apic_ctx* ctx, Grain& g, double* r2, double* b2, double* e2 = nullptr) {
+    double h[3];
+    HIPCHK(ctx, hipMemcpyAsync(h, &g.ctr->norm2, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     *r2 = h[0];
     if (b2) *b2 = h[1];
+    if (e2) *e2 = h[2];
     return APIC_OK;
 }
 
@@ -113,12 +114,28 @@ int read_norms(apic_ctx* ctx, Grain& g, double* r2, double* b2) {
 // boundary values set; stops at |D^-1 r| <= tol |D^-1 b| (b includes the
 // boundary coupling, D is the diagonal of the operator), at stagnation
 // (standalone solves), or after max_cycles.
-int solve_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_floor, int* cycles) {
+int solve_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_floor, int* cycles,
+                bool extrapolate = false) {
     HIPCHK(ctx, launch_set_boundary(ctx, g));
     HIPCHK(ctx, mg_rhs_norm(ctx, g, &g.ctr->norm2_b));
     HIPCHK(ctx, mg_residual_norm(ctx, g, &g.ctr->norm2));
-    double r2 = 0, b2 = 0;
-    TRY(read_norms(ctx, g, &r2, &b2));
+    // in the time loop the starting guess is the previous potential, or its
+    // linear extrapolation from the two previous steps when that has the
+    // smaller residual (a smooth evolution favours it, noise does not)
+    const bool try_ex = extrapolate && g.have_prev;
+    if (try_ex) {
+        HIPCHK(ctx, launch_extrapolate(ctx, g));
+        HIPCHK(ctx, mg_residual_norm(ctx, g, &g.ctr->norm2_e));
+    } else if (extrapolate) {
+        HIPCHK(ctx, launch_copy(ctx, g.phi_prev, g.mg[0].u, g.nodes));
+    }
+    double r2 = 0, b2 = 0, e2 = 0;
+    TRY(read_norms(ctx, g, &r2, &b2, &e2));
+    if (try_ex) {
+        if (e2 < r2) r2 = e2;
+        else HIPCHK(ctx, launch_copy(ctx, g.mg[0].u, g.phi_prev, g.nodes));
+    }
+    if (extrapolate) g.have_prev = true;
     const double bnorm = std::sqrt(b2 + g.bnd_norm2);
     double r = std::sqrt(r2), prev = r;
     int c = 0;
@@ -149,6 +166,7 @@ int rebuild_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_f
     ctx->timed_mg_cycles += ctx->profiling ? cyc : 0;
     HIPCHK(ctx, launch_gradient(ctx, g));
     g.field_stale = false;
+    g.have_prev = false;
     return APIC_OK;
 }
 
@@ -182,6 +200,7 @@ void free_grain(Grain& g) {
     F(g.vol);
     F(g.grad);
     F(g.rho);
+    F(g.phi_prev);
     F(g.tally);
     F(g.tally_count);
     F(g.axis_nn);
@@ -297,6 +316,7 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
     TRY(alloc_t(ctx, &g.vol, (size_t)g.nodes));
     TRY(dev_alloc(ctx, &g.grad, 2 * fsz * (size_t)g.nodes));
     TRY(alloc_t(ctx, &g.rho, (size_t)g.nodes));
+    TRY(alloc_t(ctx, &g.phi_prev, (size_t)g.nodes));
     TRY(alloc_t(ctx, &g.tally, (size_t)5 * g.ns * gp.n_bins));
     TRY(alloc_t(ctx, &g.tally_count, (size_t)g.ns * gp.n_bins));
     // sort tiles: the smallest square power-of-two tile giving at most 8192 tiles
@@ -403,7 +423,7 @@ int do_step(apic_ctx* ctx, Grain& g) {
             HIPCHK(ctx, launch_rho(ctx, g));
             HIPCHK(ctx, launch_rhs_from_rho(ctx, g));
             int cyc = 0;
-            TRY(solve_field(ctx, g, tol, maxc, false, &cyc));
+            TRY(solve_field(ctx, g, tol, maxc, false, &cyc, true));
             if (ctx->profiling) ctx->timed_mg_cycles += cyc;
             HIPCHK(ctx, launch_gradient(ctx, g));
         }
@@ -558,6 +578,7 @@ int apic_solve_poisson(apic_ctx* ctx, int32_t grain, const double* rho, double* 
         TRY(solve_field(ctx, g, 1e-15, 100, true, nullptr));
         HIPCHK(ctx, launch_gradient(ctx, g));
         g.field_stale = false;
+        g.have_prev = false;
     } else {
         TRY(rebuild_field(ctx, g, 1e-15, 100, true));
     }

@@ -48,6 +48,7 @@ struct DevCounters {
     double F_el_sum;                          // sum of per-step electric force
     double norm2;                             // scratch for residual norms
     double norm2_b;
+    double norm2_e;
 };
 
 // Particle buffers of one species: SoA.  FP32 split: pos0 = int32 packed cell,
@@ -93,6 +94,8 @@ struct Grain {
     void* grad = nullptr;           // float2 / double2 nodal (dphi/dx1, dphi/dx2)
     void* dep[APIC_MAX_SPECIES] = {nullptr, nullptr};  // float / double deposit sums
     double* rho = nullptr;          // charge density of the last deposit
+    double* phi_prev = nullptr;     // potential of the previous step (initial-guess extrapolation)
+    bool have_prev = false;
     double* tally = nullptr;        // [5][ns][n_bins]: charge, pR, pZ, L, energy
     unsigned long long* tally_count = nullptr;   // [ns][n_bins]
     double* axis_nn = nullptr;      // level-0 second-neighbour coefficient on row i2 = 0
@@ -155,6 +158,8 @@ hipError_t launch_rhs_from_rho(apic_ctx* ctx, Grain& g);
 hipError_t launch_gradient(apic_ctx* ctx, Grain& g);
 hipError_t launch_grain_force(apic_ctx* ctx, Grain& g);
 hipError_t launch_set_boundary(apic_ctx* ctx, Grain& g);
+hipError_t launch_extrapolate(apic_ctx* ctx, Grain& g);
+hipError_t launch_copy(apic_ctx* ctx, double* dst, const double* src, int n);
 
 // multigrid.hip
 hipError_t mg_vcycle(apic_ctx* ctx, Grain& g);

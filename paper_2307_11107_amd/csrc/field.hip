@@ -81,6 +81,32 @@ hipError_t launch_set_boundary(apic_ctx* ctx, Grain& g) {
     return hipGetLastError();
 }
 
+// Initial guess for the next solve: u <- 2 u - prev, prev <- old u (linear
+// extrapolation in time from the two previous potentials).
+__global__ void k_extrapolate(int nodes, double* __restrict__ u, double* __restrict__ prev) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nodes) return;
+    const double now = u[i];
+    u[i] = 2.0 * now - prev[i];
+    prev[i] = now;
+}
+
+hipError_t launch_extrapolate(apic_ctx* ctx, Grain& g) {
+    hipLaunchKernelGGL(k_extrapolate, dim3((g.nodes + 255) / 256), dim3(256), 0, ctx->stream, g.nodes,
+                       g.mg[0].u, g.phi_prev);
+    return hipGetLastError();
+}
+
+__global__ void k_copy(int n, double* __restrict__ dst, const double* __restrict__ src) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy(apic_ctx* ctx, double* dst, const double* src, int n) {
+    hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, dst, src);
+    return hipGetLastError();
+}
+
 // Nodal (dphi/dx1, dphi/dx2): central inside, second-order one-sided on the edges.
 template <typename V>
 __global__ void k_gradient(int n1, int n2, double ih1, double ih2, const double* __restrict__ phi,
