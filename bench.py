@@ -158,7 +158,7 @@ def main():
                    "particles_per_species": w["n_macro"], "grid": [w["n1"], w["n2"]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch),
-                     "kernel": "k_push<true> (FP32 split push+gather+deposit)", "avg_launch_ms": push_avg_ms,
+                     "kernel": "k_push_split (FP32 split push+gather+deposit, all species in one launch)", "avg_launch_ms": push_avg_ms,
                      "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"]},
         "breakdown_ms_per_step": {k: tm[k] / max(tm["steps"], 1) for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
         "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1),

@@ -88,7 +88,7 @@ typedef struct {
     int32_t sort_every;         /* re-sort particles by cell every k steps (0: 8)          */
     double poisson_tol;         /* in-step solves: stop at |r| <= tol |b| (0: 1e-10)       */
     int32_t poisson_max_cycles; /* in-step multigrid cycle cap (0: 40)                     */
-    int32_t reserved;
+    int32_t autotune;           /* 1: the first steps choose the launch schedule (below)   */
     void* stream;               /* hipStream_t; NULL: default stream                       */
 } apic_opts;
 
@@ -127,11 +127,28 @@ typedef struct {
     int64_t mg_cycles;     /* multigrid cycles run in timed steps               */
 } apic_kernel_times;
 
+/* Launch schedule of the particle kernels.  With apic_opts.autotune the first
+ * ~24 steps (each a real step of the run) time candidate schedules with HIP
+ * events and keep the fastest: persistent push workgroups per compute unit,
+ * the sort tile edge, and the sort interval k minimising (sort time + sum of
+ * the k following push times) / k.  Results do not depend on the schedule
+ * beyond the summation order of the deposit. */
+typedef struct {
+    int32_t push_wg_per_cu;  /* persistent push workgroups per compute unit (at
+                                most what stays resident at once)                 */
+    int32_t tile_log2;       /* preferred sort tile edge, log2 cells (each grain
+                                caps its tile count at 8192)                      */
+    int32_t sort_every;      /* steps between sorts                                */
+    int32_t tuned;           /* 1 once the autotuner has finished                   */
+} apic_sched;
 typedef struct apic_ctx apic_ctx;
 
-/* Creates a context for n_grains grains (cfgs[n_grains]), allocates device
- * memory, builds the geometry tables (node volumes from eq. 5, the eq. 7
- * stencil, the outer area from eq. 4) and the multigrid hierarchy.
+/* Creates a context for an ensemble of n_grains grains (cfgs[n_grains]; grids,
+ * shapes, fields and particle counts may all differ), allocates device memory,
+ * builds the geometry tables (node volumes from eq. 5, the eq. 7 stencil, the
+ * outer area from eq. 4) and the multigrid hierarchies.  Every step of the
+ * ensemble runs as one sequence of launches over all grains (one persistent
+ * particle launch for all grains and species), captured into HIP graphs.
  * Returns APIC_ERANGE for |alpha| >= 1/4 or x1_out outside (-1, 0).
  * *out receives the context (NULL on failure; apic_last_error(NULL) then
  * returns the message). */
@@ -149,7 +166,10 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n,
                 const double* x1, const double* x2,
                 const double* vR, const double* vZ, const double* vTheta);
 
-/* Advances every grain by n_steps (asynchronous on the context's stream). */
+/* Advances every grain by n_steps on the context's stream.  Each step reads
+ * the multigrid convergence state once (one stream synchronisation); the call
+ * returns APIC_ENOMEM if injection ran out of particle slots (the particles
+ * that did not fit are dropped and not counted as injected). */
 int apic_step(apic_ctx* ctx, int64_t n_steps);
 
 /* FP64 solve of eqs. (6)-(7) for one grain.  rho (host, (n1+1)(n2+1), units e n0)
@@ -179,6 +199,8 @@ int apic_fields(apic_ctx* ctx, int32_t grain, double* phi, double* rho);
 int apic_set_profiling(apic_ctx* ctx, int32_t on);
 int apic_timing(apic_ctx* ctx, apic_kernel_times* out);
 
+/* Copies the context's launch schedule (the autotuner's choice once tuned). */
+int apic_schedule(apic_ctx* ctx, apic_sched* out);
 /* Releases the context and its device memory. */
 int apic_free(apic_ctx* ctx);
 

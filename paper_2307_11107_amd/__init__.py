@@ -59,10 +59,11 @@ def grain_cfg(alpha, n1, n2, species_list, x1_out=-0.1, wce=0.0, kappa=1.0, phi_
 
 
 def opts(precision=APIC_FP32_SPLIT, inject=True, frozen_field=False, sort_every=0,
-         poisson_tol=0.0, poisson_max_cycles=0, stream=None):
+         poisson_tol=0.0, poisson_max_cycles=0, stream=None, autotune=False):
     o = apic_opts()
     o.precision, o.inject, o.frozen_field, o.sort_every = precision, int(inject), int(frozen_field), sort_every
     o.poisson_tol, o.poisson_max_cycles = poisson_tol, poisson_max_cycles
+    o.autotune = int(autotune)
     o.stream = stream
     return o
 
@@ -138,6 +139,13 @@ def apic_particles(ctx, grain, sp, cap):
     out = {k: v[:m].copy() for k, v in bufs.items()}
     out["id"] = ids[:m].copy()
     return out
+
+
+def apic_schedule(ctx):
+    """The context's launch schedule: dict push_wg_per_cu, tile_log2, sort_every, tuned."""
+    sc = _abi.apic_sched()
+    _check(lib().apic_schedule(ctx, C.byref(sc)), ctx)
+    return {k: int(getattr(sc, k)) for k in ("push_wg_per_cu", "tile_log2", "sort_every", "tuned")}
 
 
 def apic_fields(ctx, grain, shape):

@@ -27,7 +27,7 @@ class apic_grain_cfg(C.Structure):
 class apic_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inject", C.c_int32), ("frozen_field", C.c_int32),
                 ("sort_every", C.c_int32), ("poisson_tol", C.c_double),
-                ("poisson_max_cycles", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("poisson_max_cycles", C.c_int32), ("autotune", C.c_int32), ("stream", C.c_void_p)]
 
 
 class apic_tally(C.Structure):
@@ -47,6 +47,11 @@ class apic_kernel_times(C.Structure):
                 ("particle_steps", C.c_int64), ("mg_cycles", C.c_int64)]
 
 
+class apic_sched(C.Structure):
+    _fields_ = [("push_wg_per_cu", C.c_int32), ("tile_log2", C.c_int32), ("sort_every", C.c_int32),
+                ("tuned", C.c_int32)]
+
+
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libapic.so")
 
 # exported symbol -> (restype, argtypes)
@@ -62,6 +67,7 @@ PROTOTYPES = {
     "apic_fields": (C.c_int, [C.c_void_p, C.c_int32, _D, _D]),
     "apic_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "apic_timing": (C.c_int, [C.c_void_p, C.POINTER(apic_kernel_times)]),
+    "apic_schedule": (C.c_int, [C.c_void_p, C.POINTER(apic_sched)]),
     "apic_free": (C.c_int, [C.c_void_p]),
     "apic_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -1,8 +1,10 @@
 // C ABI of the aspherical PIC particle loop (declared in include/apic.h):
 // context set-up, particle loading, the time step, the Poisson solve, tallies
 // and read-back.  All arithmetic of the loop runs in the HIP kernels; this file
-// validates arguments, builds the FP64 geometry tables once, orders the
-// kernel launches on the context's stream and moves data across the ABI.
+// validates arguments, builds the FP64 geometry tables once, builds the
+// ensemble's descriptor tables, orders the kernel launches on the context's
+// stream (captured into HIP graphs and replayed), runs the autotuner and moves
+// data across the ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,6 +12,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "apic_internal.h"
@@ -36,6 +39,12 @@ int fail(apic_ctx* ctx, int code, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));                 \
     } while (0)
 
+#define TRY(x)                   \
+    do {                         \
+        int rc_ = (x);           \
+        if (rc_ != APIC_OK) return rc_; \
+    } while (0)
+
 int dev_alloc(apic_ctx* ctx, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return APIC_OK;
@@ -56,13 +65,7 @@ int alloc_t(apic_ctx* ctx, T** p, size_t count) {
     return rc;
 }
 
-#define TRY(x)                   \
-    do {                         \
-        int rc_ = (x);           \
-        if (rc_ != APIC_OK) return rc_; \
-    } while (0)
-
-
+// HIP-event timer of one phase on the context's stream (profiling only).
 struct Timer {
     apic_ctx* ctx;
     int kind;
@@ -99,74 +102,123 @@ struct Timer {
     }
 };
 
+bool split_mode(const apic_ctx* ctx) { return ctx->opts.precision == APIC_FP32_SPLIT; }
+bool frozen_mode(const apic_ctx* ctx) { return ctx->opts.frozen_field != 0; }
+double step_tol(const apic_ctx* ctx) { return ctx->opts.poisson_tol > 0 ? ctx->opts.poisson_tol : 1e-10; }
+int step_max_cycles(const apic_ctx* ctx) {
+    return ctx->opts.poisson_max_cycles > 0 ? ctx->opts.poisson_max_cycles : 40;
+}
+
+// ---------------------------------------------------------------- graphs
+void drop_graphs(apic_ctx* ctx) {
+    for (auto& g : ctx->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Issues the launch sequence `fn` on the stream: captured into graph `id` the
+// first time and replayed afterwards (eager if the stream cannot be captured).
+template <typename F>
+int run_phase(apic_ctx* ctx, int id, F fn) {
+    if (!ctx->graph[id] && ctx->graphs && !ctx->tuning) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            fn();
+            e = hipStreamEndCapture(ctx->stream, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph[id], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->graph[id] = nullptr;
+            ctx->graphs = false;
+            drop_graphs(ctx);
+        }
+    }
+    if (ctx->graph[id]) HIPCHK(ctx, hipGraphLaunch(ctx->graph[id], ctx->stream));
+    else {
+        fn();
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return APIC_OK;
+}
+
 // ---------------------------------------------------------------- Poisson driver
-int read_norms(apic_ctx* ctx, Grain& g, double* r2, double* b2, double* e2 = nullptr) {
-    double h[3];
-    HIPCHK(ctx, hipMemcpyAsync(h, &g.ctr->norm2, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+int read_batch(apic_ctx* ctx, MGBatch& b) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->mgb_host, ctx->mgb, sizeof(MGBatch), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    *r2 = h[0];
-    if (b2) *b2 = h[1];
-    if (e2) *e2 = h[2];
+    b = *ctx->mgb_host;
     return APIC_OK;
 }
 
-// Multigrid cycles on the current right-hand side (mg[0].f) with phi's
-// boundary values set; stops at |D^-1 r| <= tol |D^-1 b| (b includes the
-// boundary coupling, D is the diagonal of the operator), at stagnation
-// (standalone solves), or after max_cycles.
-int solve_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_floor, int* cycles,
-                bool extrapolate = false) {
-    HIPCHK(ctx, launch_set_boundary(ctx, g));
-    HIPCHK(ctx, mg_rhs_norm(ctx, g, &g.ctr->norm2_b));
-    HIPCHK(ctx, mg_residual_norm(ctx, g, &g.ctr->norm2));
-    // in the time loop the starting guess is the previous potential, or its
-    // linear extrapolation from the two previous steps when that has the
-    // smaller residual (a smooth evolution favours it, noise does not)
-    const bool try_ex = extrapolate && g.have_prev;
-    if (try_ex) {
-        HIPCHK(ctx, launch_extrapolate(ctx, g));
-        HIPCHK(ctx, mg_residual_norm(ctx, g, &g.ctr->norm2_e));
-    } else if (extrapolate) {
-        HIPCHK(ctx, launch_copy(ctx, g.phi_prev, g.mg[0].u, g.nodes));
+// Multigrid solve of every grain (only >= 0: that grain alone) on the current
+// right-hand sides.  A grain stops at |D^-1 r| <= tol |D^-1 b| (b with the
+// boundary coupling, D the operator's diagonal); standalone solves (to_floor)
+// also stop at stagnation.  In-step solves replay the captured V-cycle as many
+// times as the previous solve needed before reading the convergence state once
+// (cycles after convergence do nothing on the device).
+int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
+    MGBatch b;
+    int launched = 0;
+    if (in_step) {
+        TRY(run_phase(ctx, G_PRE, [&] {
+            (void)launch_rho_rhs(ctx);
+            (void)launch_set_boundary(ctx);
+            (void)mg_begin(ctx, tol, -1);
+        }));
+        const int pred = std::min(ctx->pred_cycles, max_cycles);
+        for (; launched < pred; ++launched)
+            TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+        TRY(read_batch(ctx, b));
+        while (b.pending > 0 && launched < max_cycles) {
+            TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+            ++launched;
+            TRY(read_batch(ctx, b));
+        }
+        ctx->pred_cycles = b.max_cycles;
+    } else {
+        HIPCHK(ctx, launch_set_boundary(ctx));
+        HIPCHK(ctx, mg_begin(ctx, tol, only));
+        TRY(read_batch(ctx, b));
+        double prev = HUGE_VAL;
+        while (b.pending > 0 && launched < max_cycles) {
+            HIPCHK(ctx, mg_vcycle_launches(ctx, tol));
+            ++launched;
+            TRY(read_batch(ctx, b));
+            if (to_floor) {
+                // largest relative residual of the grains still iterating
+                const int G = (int)ctx->grains.size();
+                std::vector<MGState> m(G);
+                HIPCHK(ctx, hipMemcpy(m.data(), ctx->mgs, sizeof(MGState) * G, hipMemcpyDeviceToHost));
+                double r = 0.0;
+                for (int g = 0; g < G; ++g)
+                    if (only < 0 || g == only)
+                        r = std::max(r, std::sqrt(m[g].last_r2 / (m[g].b2 + ctx->gdesc_h[g].bnd2 + 1e-300)));
+                if (launched >= 4 && r > 0.6 * prev) break;
+                prev = r;
+            }
+        }
     }
-    double r2 = 0, b2 = 0, e2 = 0;
-    TRY(read_norms(ctx, g, &r2, &b2, &e2));
-    if (try_ex) {
-        if (e2 < r2) r2 = e2;
-        else HIPCHK(ctx, launch_copy(ctx, g.mg[0].u, g.phi_prev, g.nodes));
+    if (b.nan) {
+        HIPCHK(ctx, launch_fill(ctx, &ctx->mgb->nan, sizeof(int)));
+        return fail(ctx, APIC_EDEVICE, "Poisson solve produced NaN");
     }
-    if (extrapolate) g.have_prev = true;
-    const double bnorm = std::sqrt(b2 + g.bnd_norm2);
-    double r = std::sqrt(r2), prev = r;
-    int c = 0;
-    while (c < max_cycles && r > tol * bnorm) {
-        HIPCHK(ctx, mg_vcycle(ctx, g));   // also leaves the new residual norm in ctr->norm2
-        TRY(read_norms(ctx, g, &r2, nullptr));
-        r = std::sqrt(r2);
-        ++c;
-        if (to_floor && c >= 4 && r > 0.6 * prev) break;
-        prev = r;
-    }
-    if (!(r == r)) return fail(ctx, APIC_EDEVICE, "Poisson solve produced NaN");
-    if (cycles) *cycles = c;
+    if (cycles) *cycles = b.max_cycles;
     return APIC_OK;
 }
 
-// Deposit the current particles and solve for phi.
-int rebuild_field(apic_ctx* ctx, Grain& g, double tol, int max_cycles, bool to_floor) {
-    const size_t dbytes = (ctx->opts.precision == APIC_FP32_SPLIT ? 4 : 8) * (size_t)g.nodes;
-    for (int s = 0; s < g.ns; ++s) {
-        HIPCHK(ctx, launch_fill(ctx, g.dep[s], dbytes));
-        HIPCHK(ctx, launch_deposit_all(ctx, g, s));
-    }
-    HIPCHK(ctx, launch_rho(ctx, g));
-    HIPCHK(ctx, launch_rhs_from_rho(ctx, g));
+// Deposit the current particles of every grain and solve for phi.
+int rebuild_fields(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only) {
+    HIPCHK(ctx, launch_clear_deposits(ctx));
+    HIPCHK(ctx, launch_deposit(ctx));
+    HIPCHK(ctx, launch_rho_rhs(ctx));
     int cyc = 0;
-    TRY(solve_field(ctx, g, tol, max_cycles, to_floor, &cyc));
-    ctx->timed_mg_cycles += ctx->profiling ? cyc : 0;
-    HIPCHK(ctx, launch_gradient(ctx, g));
-    g.field_stale = false;
-    g.have_prev = false;
+    TRY(solve(ctx, tol, max_cycles, to_floor, only, false, &cyc));
+    HIPCHK(ctx, launch_gradient(ctx));
+    for (size_t g = 0; g < ctx->grains.size(); ++g)
+        if (only < 0 || (int)g == only) ctx->grains[g].field_stale = false;
     return APIC_OK;
 }
 
@@ -194,31 +246,50 @@ void free_grain(Grain& g) {
             b = PBuf();
         }
         F(g.dep[s]);
+        F(g.hist[s]);
+        F(g.hist_off[s]);
+        F(g.seg[s]);
         g.dep[s] = nullptr;
+        g.hist[s] = g.hist_off[s] = g.seg[s] = nullptr;
     }
     F(g.ctr);
     F(g.vol);
     F(g.grad);
     F(g.rho);
-    F(g.phi_prev);
     F(g.tally);
     F(g.tally_count);
     F(g.axis_nn);
     F(g.axis_ss);
     F(g.coarse_inv);
-    F(g.sort_count);
-    F(g.sort_offset);
-    F(g.scan_tmp);
-    if (g.vcycle_exec) (void)hipGraphExecDestroy(g.vcycle_exec);
-    g.vcycle_exec = nullptr;
     for (auto& L : g.mg) {
         F(L.st);
         F(L.u);
         F(L.f);
-        F(L.r);
     }
     g.mg.clear();
     g.ctr = nullptr;
+}
+
+void free_ctx(apic_ctx* ctx) {
+    drop_graphs(ctx);
+    for (auto& g : ctx->grains) free_grain(g);
+    auto F = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    F(ctx->tasks);
+    F(ctx->chunk_prefix);
+    F(ctx->gdesc);
+    F(ctx->mgdesc);
+    F(ctx->mgs);
+    F(ctx->norm_part);
+    F(ctx->mgb);
+    if (ctx->mgb_host) (void)hipHostFree(ctx->mgb_host);
+    for (auto& t : ctx->timers) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
 }
 
 int validate_cfg(const apic_grain_cfg& c) {
@@ -237,7 +308,29 @@ int validate_cfg(const apic_grain_cfg& c) {
     return APIC_OK;
 }
 
-int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
+// Smallest square power-of-two tile (at least 2^want cells) giving at most
+// 8192 tiles on an n1 x n2 grid.
+int tile_log2_for(int n1, int n2, int want) {
+    int t = std::max(want, 2);
+    while (((n1 + (1 << t) - 1) >> t) * ((n2 + (1 << t) - 1) >> t) > 8192) ++t;
+    return t;
+}
+
+void set_tiles(GrainParams& gp, int t) {
+    gp.tile_log2 = t;
+    gp.ntx = (gp.n1 + (1 << t) - 1) >> t;
+    gp.ntiles = gp.ntx * ((gp.n2 + (1 << t) - 1) >> t);
+}
+
+// Host part of a grain's set-up (no HIP calls; grains are set up in parallel).
+struct HostSetup {
+    std::vector<Stencil> levels;
+    std::vector<double> inv;
+    int rc = APIC_OK;
+    std::string err;
+};
+
+void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     g.cfg = c;
     g.ns = c.n_species;
     const int n1 = c.n1, n2 = c.n2, nx = n1 + 1;
@@ -262,6 +355,7 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
     gp.M_area = bound_outer_area_density(c.x1_out, c.alpha);
     gp.key0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
     gp.key1 = (uint32_t)((c.seed >> 32) + (uint64_t)gi);
+    set_tiles(gp, tile_log2_for(n1, n2, 3));
 
     node_volumes(n1, n2, c.x1_out, c.alpha, g.vol_host);
     g.V = 0.0;
@@ -285,19 +379,61 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
         p.sigma = std::sqrt(a.T / a.m);
         const double flux = a.n * std::sqrt(a.T / (2.0 * M_PI * a.m));
         const double n_real = p.w > 0 ? flux * g.A_out * c.kappa * c.dt / p.w : 0.0;
-        if (n_real > 1e12) return fail(ctx, APIC_ERANGE, "injection rate too large");
+        if (n_real > 1e9) {
+            hs.rc = APIC_ERANGE;
+            hs.err = "injection rate too large";
+            return;
+        }
         g.inj_inc[s] = (uint64_t)std::llround(n_real * 4294967296.0);
-        g.inj_acc[s] = 0;
         int64_t cap = a.capacity;
         if (cap == 0) cap = (int64_t)(1.5 * (double)a.n_macro) + 64 * (int64_t)std::ceil(n_real) + 4096;
-        if (cap > (int64_t)2000000000) return fail(ctx, APIC_ERANGE, "particle capacity above 2^31");
+        if (cap > (int64_t)2000000000) {
+            hs.rc = APIC_ERANGE;
+            hs.err = "particle capacity above 2^31";
+            return;
+        }
         g.capacity[s] = cap;
-        g.host_slots[s] = 0;
+        // sort workgroups: about 32k slots each, a power of two in [16, 1024]
+        int sb = 16;
+        while (sb < max_sort_blocks() && (int64_t)sb * 32768 < cap) sb <<= 1;
+        g.sort_blocks[s] = sb;
     }
 
-    // ---- device allocations
-    const bool split = ctx->opts.precision == APIC_FP32_SPLIT;
+    // multigrid hierarchy: coarsen by two while both cell counts are even and
+    // at least 8, and stop at the first level with at most 600 nodes (solved
+    // by a dense inverse)
+    hs.levels.resize(1);
+    fine_stencil(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
+    while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > 600 && hs.levels.back().n1 % 2 == 0 &&
+           hs.levels.back().n2 % 2 == 0 && std::min(hs.levels.back().n1, hs.levels.back().n2) / 2 >= 4) {
+        Stencil cs;
+        galerkin_coarse(hs.levels.back(), cs);
+        hs.levels.push_back(std::move(cs));
+    }
+    const Stencil& last = hs.levels.back();
+    const int m = (last.n1 + 1) * (last.n2 + 1);
+    if (m > 4096) {
+        hs.rc = APIC_ERANGE;
+        hs.err = "grid does not coarsen far enough for multigrid";
+        return;
+    }
+    std::vector<double> A;
+    dense_matrix(last, A);
+    if (!invert(A, m, hs.inv)) {
+        hs.rc = APIC_EDEVICE;
+        hs.err = "coarsest multigrid operator is singular";
+        return;
+    }
+    g.coarse_nodes = m;
+    g.bnd_norm2 = boundary_coupling_norm2(hs.levels[0], c.phi_grain, c.phi_out);
+}
+
+// Device part of a grain's set-up.
+int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
+    const bool split = split_mode(ctx);
     const size_t fsz = split ? 4 : 8;
+    const int min_tile = tile_log2_for(g.gp.n1, g.gp.n2, 2);
+    const int max_tiles = ((g.gp.n1 + (1 << min_tile) - 1) >> min_tile) * ((g.gp.n2 + (1 << min_tile) - 1) >> min_tile);
     for (int s = 0; s < g.ns; ++s) {
         const size_t cap = (size_t)g.capacity[s];
         for (int k = 0; k < 2; ++k) {
@@ -311,131 +447,383 @@ int setup_grain(apic_ctx* ctx, Grain& g, const apic_grain_cfg& c, int gi) {
             TRY(alloc_t(ctx, &b.id, cap));
         }
         TRY(dev_alloc(ctx, &g.dep[s], fsz * (size_t)g.nodes));
+        const size_t hist_len = (size_t)max_tiles * g.sort_blocks[s];
+        TRY(alloc_t(ctx, &g.hist[s], hist_len));
+        TRY(alloc_t(ctx, &g.hist_off[s], hist_len + 1));
+        TRY(alloc_t(ctx, &g.seg[s], hist_len / scan_seg_len() + 2));
+        HIPCHK(ctx, launch_fill(ctx, g.dep[s], fsz * (size_t)g.nodes));
     }
     TRY(alloc_t(ctx, &g.ctr, 1));
     TRY(alloc_t(ctx, &g.vol, (size_t)g.nodes));
     TRY(dev_alloc(ctx, &g.grad, 2 * fsz * (size_t)g.nodes));
     TRY(alloc_t(ctx, &g.rho, (size_t)g.nodes));
-    TRY(alloc_t(ctx, &g.phi_prev, (size_t)g.nodes));
-    TRY(alloc_t(ctx, &g.tally, (size_t)5 * g.ns * gp.n_bins));
-    TRY(alloc_t(ctx, &g.tally_count, (size_t)g.ns * gp.n_bins));
-    // sort tiles: the smallest square power-of-two tile giving at most 8192 tiles
-    gp.tile_log2 = 3;
-    while (((n1 + (1 << gp.tile_log2) - 1) >> gp.tile_log2) * ((n2 + (1 << gp.tile_log2) - 1) >> gp.tile_log2) > 8192)
-        ++gp.tile_log2;
-    gp.ntx = (n1 + (1 << gp.tile_log2) - 1) >> gp.tile_log2;
-    gp.ntiles = gp.ntx * ((n2 + (1 << gp.tile_log2) - 1) >> gp.tile_log2);
-    const size_t hist_len = (size_t)gp.ntiles * sort_blocks() + 1;
-    TRY(alloc_t(ctx, &g.sort_count, hist_len));
-    TRY(alloc_t(ctx, &g.sort_offset, hist_len));
-    HIPCHK(ctx, launch_fill(ctx, g.sort_count, sizeof(int) * hist_len));
-    g.scan_tmp_bytes = scan_temp_bytes((int)hist_len);
-    TRY(dev_alloc(ctx, &g.scan_tmp, g.scan_tmp_bytes));
+    TRY(alloc_t(ctx, &g.tally, (size_t)5 * g.ns * g.gp.n_bins));
+    TRY(alloc_t(ctx, &g.tally_count, (size_t)g.ns * g.gp.n_bins));
     HIPCHK(ctx, launch_fill(ctx, g.ctr, sizeof(DevCounters)));
-    HIPCHK(ctx, launch_fill(ctx, g.tally, sizeof(double) * 5 * g.ns * gp.n_bins));
-    HIPCHK(ctx, launch_fill(ctx, g.tally_count, sizeof(unsigned long long) * g.ns * gp.n_bins));
+    HIPCHK(ctx, launch_fill(ctx, g.tally, sizeof(double) * 5 * g.ns * g.gp.n_bins));
+    HIPCHK(ctx, launch_fill(ctx, g.tally_count, sizeof(unsigned long long) * g.ns * g.gp.n_bins));
     HIPCHK(ctx, launch_fill(ctx, g.rho, sizeof(double) * g.nodes));
+    HIPCHK(ctx, launch_fill(ctx, g.grad, 2 * fsz * (size_t)g.nodes));
     HIPCHK(ctx, hipMemcpyAsync(g.vol, g.vol_host.data(), sizeof(double) * g.nodes,
                                hipMemcpyHostToDevice, ctx->stream));
-
-    // ---- multigrid hierarchy
-    // coarsen by two while both cell counts are even and at least 8, and stop
-    // at the first level with at most 600 nodes (solved by a dense inverse)
-    std::vector<Stencil> levels(1);
-    fine_stencil(n1, n2, c.x1_out, c.alpha, levels[0]);
-    while ((levels.back().n1 + 1) * (levels.back().n2 + 1) > 600 && levels.back().n1 % 2 == 0 &&
-           levels.back().n2 % 2 == 0 && std::min(levels.back().n1, levels.back().n2) / 2 >= 4) {
-        Stencil cs;
-        galerkin_coarse(levels.back(), cs);
-        levels.push_back(std::move(cs));
-    }
-    const Stencil& last = levels.back();
-    const int m = (last.n1 + 1) * (last.n2 + 1);
-    if (m > 4096) return fail(ctx, APIC_ERANGE, "grid does not coarsen far enough for multigrid");
-    std::vector<double> A, inv;
-    dense_matrix(last, A);
-    if (!invert(A, m, inv)) return fail(ctx, APIC_EDEVICE, "coarsest multigrid operator is singular");
-    g.coarse_nodes = m;
-    TRY(alloc_t(ctx, &g.coarse_inv, (size_t)m * m));
+    TRY(alloc_t(ctx, &g.coarse_inv, (size_t)g.coarse_nodes * g.coarse_nodes));
     std::vector<double> stage;
-    g.mg.resize(levels.size());
-    for (size_t l = 0; l < levels.size(); ++l) {
+    g.mg.resize(hs.levels.size());
+    for (size_t l = 0; l < hs.levels.size(); ++l) {
         MGLevel& L = g.mg[l];
-        L.n1 = levels[l].n1;
-        L.n2 = levels[l].n2;
+        L.n1 = hs.levels[l].n1;
+        L.n2 = hs.levels[l].n2;
         L.nx = L.n1 + 1;
         L.nodes = L.nx * (L.n2 + 1);
         TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
         TRY(alloc_t(ctx, &L.u, (size_t)L.nodes));
         TRY(alloc_t(ctx, &L.f, (size_t)L.nodes));
-        TRY(alloc_t(ctx, &L.r, (size_t)L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.u, sizeof(double) * L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.f, sizeof(double) * L.nodes));
-        HIPCHK(ctx, launch_fill(ctx, L.r, sizeof(double) * L.nodes));
         stage.resize((size_t)ST_COUNT * L.nodes);
         for (int k = 0; k < ST_COUNT; ++k)
-            std::copy(levels[l].c[k].begin(), levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
+            std::copy(hs.levels[l].c[k].begin(), hs.levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
         HIPCHK(ctx, hipMemcpy(L.st, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice));
     }
+    const int nx = g.gp.nx;
     TRY(alloc_t(ctx, &g.axis_nn, (size_t)nx));
     TRY(alloc_t(ctx, &g.axis_ss, (size_t)nx));
-    HIPCHK(ctx, hipMemcpy(g.axis_nn, levels[0].nn.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(g.axis_ss, levels[0].ss.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(g.coarse_inv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
-    g.bnd_norm2 = boundary_coupling_norm2(levels[0], c.phi_grain, c.phi_out);
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-
-    // vacuum field until particles are loaded
-    HIPCHK(ctx, launch_fill(ctx, g.rho, sizeof(double) * g.nodes));
-    HIPCHK(ctx, launch_rhs_from_rho(ctx, g));
-    TRY(solve_field(ctx, g, 1e-15, 100, true, nullptr));
-    HIPCHK(ctx, launch_gradient(ctx, g));
-    g.field_stale = true;
+    HIPCHK(ctx, hipMemcpy(g.axis_nn, hs.levels[0].nn.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(g.axis_ss, hs.levels[0].ss.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(g.coarse_inv, hs.inv.data(), sizeof(double) * hs.inv.size(), hipMemcpyHostToDevice));
     return APIC_OK;
 }
 
-int do_step(apic_ctx* ctx, Grain& g) {
-    const bool frozen = ctx->opts.frozen_field != 0;
-    const double tol = ctx->opts.poisson_tol > 0 ? ctx->opts.poisson_tol : 1e-10;
-    const int maxc = ctx->opts.poisson_max_cycles > 0 ? ctx->opts.poisson_max_cycles : 40;
-    if (g.field_stale && !frozen) TRY(rebuild_field(ctx, g, tol, maxc, false));
-    g.field_stale = false;
-    const size_t dbytes = (ctx->opts.precision == APIC_FP32_SPLIT ? 4 : 8) * (size_t)g.nodes;
-    for (int s = 0; s < g.ns; ++s) {
-        if (!frozen) HIPCHK(ctx, launch_fill(ctx, g.dep[s], dbytes));
+// Per-task view of the ensemble for the particle kernels.
+void fill_tasks(apic_ctx* ctx) {
+    ctx->tasks_h.clear();
+    ctx->max_inj_bound = 0;
+    ctx->max_ntiles = 0;
+    ctx->max_sort_blocks = 0;
+    ctx->max_segs = 1;
+    for (size_t gi = 0; gi < ctx->grains.size(); ++gi) {
+        Grain& g = ctx->grains[gi];
+        for (int s = 0; s < g.ns; ++s) {
+            PushTask t;
+            std::memset(&t, 0, sizeof(t));
+            t.gp = g.gp;
+            t.sp = g.sp[s];
+            t.buf[0] = g.buf[s][0];
+            t.buf[1] = g.buf[s][1];
+            t.grad = g.grad;
+            t.dep = g.dep[s];
+            t.ctr = g.ctr;
+            t.tally = g.tally;
+            t.tally_count = g.tally_count;
+            t.hist = g.hist[s];
+            t.hist_off = g.hist_off[s];
+            t.seg = g.seg[s];
+            t.capacity = g.capacity[s];
+            t.inj_inc = g.inj_inc[s];
+            t.s = s;
+            t.ns = g.ns;
+            t.grain = (int)gi;
+            t.sort_blocks = g.sort_blocks[s];
+            ctx->tasks_h.push_back(t);
+            ctx->max_inj_bound = std::max<int>(ctx->max_inj_bound, (int)(g.inj_inc[s] >> 32) + 1);
+            ctx->max_ntiles = std::max(ctx->max_ntiles, g.gp.ntiles);
+            ctx->max_sort_blocks = std::max(ctx->max_sort_blocks, g.sort_blocks[s]);
+            const int64_t len = (int64_t)g.gp.ntiles * g.sort_blocks[s];
+            ctx->max_segs = std::max<int>(ctx->max_segs, (int)((len + scan_seg_len() - 1) / scan_seg_len()));
+        }
+    }
+    ctx->ntasks = (int)ctx->tasks_h.size();
+}
+
+int upload_tasks(apic_ctx* ctx) {
+    fill_tasks(ctx);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->tasks, ctx->tasks_h.data(), sizeof(PushTask) * ctx->ntasks,
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return APIC_OK;
+}
+
+// Descriptor tables of the ensemble (after every grain is set up).
+int build_tables(apic_ctx* ctx) {
+    const int G = (int)ctx->grains.size();
+    fill_tasks(ctx);
+    TRY(alloc_t(ctx, &ctx->tasks, ctx->tasks_h.size()));
+    TRY(alloc_t(ctx, &ctx->chunk_prefix, ctx->tasks_h.size() + 1));
+    TRY(upload_tasks(ctx));
+
+    ctx->gdesc_h.assign(G, GrainDesc());
+    ctx->n_levels = 0;
+    ctx->max_nodes = ctx->max_n1 = ctx->max_n2 = 0;
+    for (int gi = 0; gi < G; ++gi) {
+        Grain& g = ctx->grains[gi];
+        GrainDesc& d = ctx->gdesc_h[gi];
+        std::memset(&d, 0, sizeof(d));
+        d.n1 = g.gp.n1;
+        d.n2 = g.gp.n2;
+        d.nx = g.gp.nx;
+        d.nodes = g.nodes;
+        d.ns = g.ns;
+        d.inv_h1 = g.gp.inv_h1;
+        d.inv_h2 = g.gp.inv_h2;
+        d.h2 = g.gp.h2;
+        d.alpha = g.gp.alpha;
+        d.rhs_scale = -1.0 / (g.gp.kappa * g.gp.kappa);
+        d.phi_grain = g.cfg.phi_grain;
+        d.phi_out = g.cfg.phi_out;
+        for (int s = 0; s < g.ns; ++s) {
+            d.cw[s] = g.sp[s].q * g.sp[s].w;
+            d.dep[s] = g.dep[s];
+        }
+        d.bnd2 = g.bnd_norm2;
+        d.vol = g.vol;
+        d.rho = g.rho;
+        d.u = g.mg[0].u;
+        d.f = g.mg[0].f;
+        d.diag = g.mg[0].st;
+        d.grad = g.grad;
+        d.ctr = g.ctr;
+        ctx->n_levels = std::max(ctx->n_levels, (int)g.mg.size());
+        ctx->max_nodes = std::max(ctx->max_nodes, g.nodes);
+        ctx->max_n1 = std::max(ctx->max_n1, g.gp.n1);
+        ctx->max_n2 = std::max(ctx->max_n2, g.gp.n2);
+    }
+    TRY(alloc_t(ctx, &ctx->gdesc, (size_t)G));
+    HIPCHK(ctx, hipMemcpy(ctx->gdesc, ctx->gdesc_h.data(), sizeof(GrainDesc) * G, hipMemcpyHostToDevice));
+
+    const int NL = ctx->n_levels;
+    ctx->mgdesc_h.assign((size_t)NL * G, MGDesc());
+    ctx->lvl_max_n1.assign(NL, 0);
+    ctx->lvl_max_n2.assign(NL, 0);
+    ctx->lvl_max_nodes.assign(NL, 0);
+    ctx->lvl_lines_x2.assign(NL, 0);
+    ctx->lvl_max_m.assign(NL, 0);
+    for (int l = 0; l < NL; ++l)
+        for (int gi = 0; gi < G; ++gi) {
+            MGDesc& d = ctx->mgdesc_h[(size_t)l * G + gi];
+            std::memset(&d, 0, sizeof(d));
+            Grain& g = ctx->grains[gi];
+            if (l >= (int)g.mg.size()) continue;
+            const MGLevel& L = g.mg[l];
+            d.n1 = L.n1;
+            d.n2 = L.n2;
+            d.nx = L.nx;
+            d.nodes = L.nodes;
+            d.coarsest = l + 1 == (int)g.mg.size();
+            d.m = d.coarsest ? g.coarse_nodes : 0;
+            d.st = L.st;
+            d.u = L.u;
+            d.f = L.f;
+            d.nn = l == 0 ? g.axis_nn : nullptr;
+            d.ss = l == 0 ? g.axis_ss : nullptr;
+            d.inv = d.coarsest ? g.coarse_inv : nullptr;
+            ctx->lvl_max_n1[l] = std::max(ctx->lvl_max_n1[l], L.n1);
+            ctx->lvl_max_n2[l] = std::max(ctx->lvl_max_n2[l], L.n2);
+            ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
+            if (!d.coarsest) ctx->lvl_lines_x2[l] += L.n1 / 2;
+            else ctx->lvl_max_m[l] = std::max(ctx->lvl_max_m[l], d.m);
+        }
+    TRY(alloc_t(ctx, &ctx->mgdesc, ctx->mgdesc_h.size()));
+    HIPCHK(ctx, hipMemcpy(ctx->mgdesc, ctx->mgdesc_h.data(), sizeof(MGDesc) * ctx->mgdesc_h.size(),
+                          hipMemcpyHostToDevice));
+    TRY(alloc_t(ctx, &ctx->mgs, (size_t)G));
+    TRY(alloc_t(ctx, &ctx->norm_part, (size_t)2 * G * ((ctx->lvl_max_nodes[0] + 255) / 256)));
+    TRY(alloc_t(ctx, &ctx->mgb, 1));
+    HIPCHK(ctx, launch_fill(ctx, ctx->mgs, sizeof(MGState) * G));
+    HIPCHK(ctx, launch_fill(ctx, ctx->mgb, sizeof(MGBatch)));
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->mgb_host, sizeof(MGBatch), hipHostMallocDefault));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return APIC_OK;
+}
+
+// Sort tiles of every grain for a preferred tile edge 2^t (each grain caps its
+// tile count at 8192); the graphs depend on the tile counts and are rebuilt.
+int apply_tiles(apic_ctx* ctx, int t) {
+    for (auto& g : ctx->grains) set_tiles(g.gp, tile_log2_for(g.gp.n1, g.gp.n2, t));
+    ctx->sched.tile_log2 = t;
+    drop_graphs(ctx);
+    return upload_tasks(ctx);
+}
+
+int sort_all(apic_ctx* ctx) {
+    TRY(run_phase(ctx, G_SORT, [&] { (void)launch_sort(ctx); }));
+    for (auto& g : ctx->grains)
+        for (int s = 0; s < g.ns; ++s) g.cur[s] = 1 - g.cur[s];
+    return APIC_OK;
+}
+
+int push_phase(apic_ctx* ctx) {
+    const bool frozen = frozen_mode(ctx);
+    return run_phase(ctx, G_PUSH, [&] {
+        if (!frozen) (void)launch_clear_deposits(ctx);
+        (void)launch_push(ctx, !frozen);
+    });
+}
+
+int sort_every(const apic_ctx* ctx) {
+    if (ctx->opts.sort_every > 0 && !ctx->opts.autotune) return ctx->opts.sort_every;
+    return ctx->sched.sort_every;
+}
+
+// One step of every grain: push (gather, kick, drift, boundaries, deposit),
+// injection, charge density, FP64 solve, nodal gradient, grain force; a sort
+// every sort_every steps.
+int do_step(apic_ctx* ctx) {
+    const bool frozen = frozen_mode(ctx);
+    bool stale = false;
+    for (auto& g : ctx->grains) stale |= g.field_stale;
+    if (stale && !frozen) TRY(rebuild_fields(ctx, step_tol(ctx), step_max_cycles(ctx), false, -1));
+    for (auto& g : ctx->grains) g.field_stale = false;
+    {
         Timer t(ctx, 0);
-        HIPCHK(ctx, launch_push(ctx, g, s));
+        TRY(push_phase(ctx));
         if (ctx->profiling) ++ctx->push_launches;
     }
     if (ctx->opts.inject) {
         Timer t(ctx, 1);
-        for (int s = 0; s < g.ns; ++s) {
-            g.inj_acc[s] += g.inj_inc[s];
-            const int64_t n_new = (int64_t)(g.inj_acc[s] >> 32);
-            g.inj_acc[s] &= 0xFFFFFFFFull;
-            if (n_new > 0)
-                HIPCHK(ctx, launch_inject(ctx, g, s, n_new, (uint32_t)(g.step_index & 0xFFFFFFFFull)));
-        }
+        TRY(run_phase(ctx, G_INJ, [&] { (void)launch_inject(ctx, !frozen); }));
     }
     {
         Timer t(ctx, 3);
         if (!frozen) {
-            HIPCHK(ctx, launch_rho(ctx, g));
-            HIPCHK(ctx, launch_rhs_from_rho(ctx, g));
             int cyc = 0;
-            TRY(solve_field(ctx, g, tol, maxc, false, &cyc, true));
+            TRY(solve(ctx, step_tol(ctx), step_max_cycles(ctx), false, -1, true, &cyc));
             if (ctx->profiling) ctx->timed_mg_cycles += cyc;
-            HIPCHK(ctx, launch_gradient(ctx, g));
         }
-        HIPCHK(ctx, launch_grain_force(ctx, g));
+        TRY(run_phase(ctx, G_POST, [&] {
+            if (!frozen) (void)launch_gradient(ctx);
+            (void)launch_grain_force(ctx);
+        }));
     }
-    g.step_index++;
-    const int k = ctx->opts.sort_every > 0 ? ctx->opts.sort_every : 8;
-    if (g.step_index % (uint64_t)k == 0) {
+    for (auto& g : ctx->grains) g.step_index++;
+    const uint64_t step = ctx->grains[0].step_index;
+    if (step % (uint64_t)sort_every(ctx) == 0) {
         Timer t(ctx, 2);
-        for (int s = 0; s < g.ns; ++s) HIPCHK(ctx, launch_sort(ctx, g, s));
+        TRY(sort_all(ctx));
     }
     if (ctx->profiling) ++ctx->timed_steps;
+    return APIC_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Chooses the launch schedule on the first steps of the run, timing real steps
+// with HIP events (every candidate gives the same particles up to the order of
+// the deposit sums):
+//   1. persistent push workgroups per CU: each candidate times one push;
+//   2. sort tile edge: each candidate sorts, then times the next push;
+//   3. sort interval: after a sort, the pushes of the following steps are
+//      timed; the interval k minimises (sort + sum of the k pushes) / k.
+struct TuneClock {
+    hipEvent_t a = nullptr, b = nullptr;
+    TuneClock() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~TuneClock() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+template <typename F>
+int timed(apic_ctx* ctx, TuneClock& c, F fn, float* ms) {
+    HIPCHK(ctx, hipEventRecord(c.a, ctx->stream));
+    TRY(fn());
+    HIPCHK(ctx, hipEventRecord(c.b, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(c.b));
+    HIPCHK(ctx, hipEventElapsedTime(ms, c.a, c.b));
+    return APIC_OK;
+}
+
+// the rest of a step after the push (injection, field, force), untimed
+int finish_step(apic_ctx* ctx) {
+    const bool frozen = frozen_mode(ctx);
+    if (ctx->opts.inject) TRY(run_phase(ctx, G_INJ, [&] { (void)launch_inject(ctx, !frozen); }));
+    if (!frozen) TRY(solve(ctx, step_tol(ctx), step_max_cycles(ctx), false, -1, true, nullptr));
+    TRY(run_phase(ctx, G_POST, [&] {
+        if (!frozen) (void)launch_gradient(ctx);
+        (void)launch_grain_force(ctx);
+    }));
+    for (auto& g : ctx->grains) g.step_index++;
+    return APIC_OK;
+}
+
+// Runs tuning steps (each a real step) while *left > 0; returns when tuning is
+// complete or the steps are used up (it resumes on the next call).
+int autotune(apic_ctx* ctx, int64_t* left) {
+    TuneState* st = &ctx->tune;
+    const int resident = push_resident_per_cu(ctx);   // candidates 1 .. resident workgroups per CU
+    const int tile_cand[] = {2, 3, 4};
+    TuneClock clk;
+    ctx->tuning = true;
+    drop_graphs(ctx);
+    bool stale = false;
+    for (auto& g : ctx->grains) stale |= g.field_stale;
+    if (stale && !frozen_mode(ctx)) TRY(rebuild_fields(ctx, step_tol(ctx), step_max_cycles(ctx), false, -1));
+    for (auto& g : ctx->grains) g.field_stale = false;
+    while (*left > 0 && !ctx->tuned) {
+        float ms = 0;
+        if (st->phase == 0) {
+            ctx->sched.push_wg_per_cu = resident - st->idx;
+            TRY(timed(ctx, clk, [&] { return push_phase(ctx); }, &ms));
+            if (ms < st->best) {
+                st->best = ms;
+                st->best_val = resident - st->idx;
+            }
+            if (++st->idx == resident) {
+                ctx->sched.push_wg_per_cu = st->best_val;
+                drop_graphs(ctx);
+                st->phase = 1;
+                st->idx = 0;
+                st->best = 1e30f;
+            }
+        } else if (st->phase == 1) {
+            TRY(apply_tiles(ctx, tile_cand[st->idx]));
+            float sms = 0;
+            TRY(timed(ctx, clk, [&] { return sort_all(ctx); }, &sms));
+            TRY(timed(ctx, clk, [&] { return push_phase(ctx); }, &ms));
+            if (ms + sms / 8 < st->best) {
+                st->best = ms + sms / 8;
+                st->best_val = tile_cand[st->idx];
+                st->sort_ms = sms;
+            }
+            if (++st->idx == 3) {
+                TRY(apply_tiles(ctx, st->best_val));
+                st->phase = 2;
+                st->idx = 0;
+            }
+        } else {
+            if (st->idx == 0) TRY(timed(ctx, clk, [&] { return sort_all(ctx); }, &st->sort_ms));
+            TRY(timed(ctx, clk, [&] { return push_phase(ctx); }, &ms));
+            st->push_after.push_back(ms);
+            if (++st->idx == 16) {
+                double best = 1e30, sum = 0;
+                int k_best = 8;
+                for (int k = 1; k <= 16; ++k) {
+                    sum += st->push_after[k - 1];
+                    const double per = (st->sort_ms + sum) / k;
+                    if (per < best) {
+                        best = per;
+                        k_best = k;
+                    }
+                }
+                ctx->sched.sort_every = k_best;
+                ctx->tuned = true;
+            }
+        }
+        TRY(finish_step(ctx));
+        --*left;
+    }
+    ctx->tuning = false;
+    return APIC_OK;
+}
+
+int check_overflow(apic_ctx* ctx) {
+    for (auto& g : ctx->grains) {
+        uint32_t of = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&of, &g.ctr->overflow, sizeof(of), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (of) return fail(ctx, APIC_ENOMEM, "particle capacity exceeded during injection");
+    }
     return APIC_OK;
 }
 
@@ -464,7 +852,7 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         delete ctx;
         return fail(nullptr, APIC_EINVAL, "precision must be APIC_FP32_SPLIT or APIC_FP64");
     }
-    int rc = APIC_OK;
+    if (ctx->opts.sort_every > 0) ctx->sched.sort_every = ctx->opts.sort_every;
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e != hipSuccess) {
@@ -484,11 +872,33 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         ctx->own_stream = true;
     }
     ctx->grains.resize(n_grains);
-    for (int i = 0; i < n_grains && rc == APIC_OK; ++i) rc = setup_grain(ctx, ctx->grains[i], cfgs[i], i);
+    // host tables of all grains in parallel, then the device side in order
+    std::vector<HostSetup> hs(n_grains);
+    {
+        const int nt = std::max(1, std::min<int>(n_grains, (int)std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (int w = 0; w < nt; ++w)
+            pool.emplace_back([&, w] {
+                for (int i = w; i < n_grains; i += nt) host_setup(ctx->grains[i], cfgs[i], i, hs[i]);
+            });
+        for (auto& t : pool) t.join();
+    }
+    int rc = APIC_OK;
+    for (int i = 0; i < n_grains && rc == APIC_OK; ++i)
+        if (hs[i].rc != APIC_OK) rc = fail(ctx, hs[i].rc, "grain " + std::to_string(i) + ": " + hs[i].err);
+    for (int i = 0; i < n_grains && rc == APIC_OK; ++i) {
+        rc = device_setup(ctx, ctx->grains[i], hs[i]);
+        hs[i] = HostSetup();
+    }
+    if (rc == APIC_OK) rc = build_tables(ctx);
+    if (rc == APIC_OK) {
+        // vacuum field until particles are loaded
+        rc = rebuild_fields(ctx, 1e-15, 100, true, -1);
+        for (auto& g : ctx->grains) g.field_stale = true;
+    }
     if (rc != APIC_OK) {
         g_init_error = ctx->err;
-        for (auto& g : ctx->grains) free_grain(g);
-        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        free_ctx(ctx);
         delete ctx;
         return rc;
     }
@@ -548,14 +958,14 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
     h.escaped[s] = 0;
     h.pushed[s] = 0;
     h.next_id[s] = (uint32_t)count;
+    h.cur[s] = 0;
     HIPCHK(ctx, hipMemcpyAsync(g.ctr, &h, sizeof(DevCounters), hipMemcpyHostToDevice, ctx->stream));
     for (int k = 0; k < 5; ++k)
         HIPCHK(ctx, launch_fill(ctx, g.tally + ((size_t)k * g.ns + s) * g.gp.n_bins,
                                 sizeof(double) * g.gp.n_bins));
     HIPCHK(ctx, launch_fill(ctx, g.tally_count + (size_t)s * g.gp.n_bins,
                             sizeof(unsigned long long) * g.gp.n_bins));
-    g.host_slots[s] = count;
-    HIPCHK(ctx, launch_sort(ctx, g, s));
+    TRY(sort_all(ctx));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     g.field_stale = true;
     return APIC_OK;
@@ -564,8 +974,10 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
 int apic_step(apic_ctx* ctx, int64_t n_steps) {
     if (!ctx) return fail(nullptr, APIC_EINVAL, "null context");
     if (n_steps < 0) return fail(ctx, APIC_EINVAL, "n_steps < 0");
-    for (int64_t k = 0; k < n_steps; ++k)
-        for (auto& g : ctx->grains) TRY(do_step(ctx, g));
+    int64_t left = n_steps;
+    if (ctx->opts.autotune && !ctx->tuned && left > 0) TRY(autotune(ctx, &left));
+    for (int64_t k = 0; k < left; ++k) TRY(do_step(ctx));
+    if (n_steps > 0) TRY(check_overflow(ctx));
     return APIC_OK;
 }
 
@@ -574,13 +986,12 @@ int apic_solve_poisson(apic_ctx* ctx, int32_t grain, const double* rho, double* 
     Grain& g = ctx->grains[grain];
     if (rho) {
         HIPCHK(ctx, hipMemcpyAsync(g.rho, rho, sizeof(double) * g.nodes, hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(ctx, launch_rhs_from_rho(ctx, g));
-        TRY(solve_field(ctx, g, 1e-15, 100, true, nullptr));
-        HIPCHK(ctx, launch_gradient(ctx, g));
+        HIPCHK(ctx, launch_rhs_from_rho(ctx, grain));
+        TRY(solve(ctx, 1e-15, 100, true, grain, false, nullptr));
+        HIPCHK(ctx, launch_gradient(ctx));
         g.field_stale = false;
-        g.have_prev = false;
     } else {
-        TRY(rebuild_field(ctx, g, 1e-15, 100, true));
+        TRY(rebuild_fields(ctx, 1e-15, 100, true, grain));
     }
     if (phi_out)
         HIPCHK(ctx, hipMemcpyAsync(phi_out, g.mg[0].u, sizeof(double) * g.nodes, hipMemcpyDeviceToHost,
@@ -741,16 +1152,19 @@ int apic_timing(apic_ctx* ctx, apic_kernel_times* out) {
     return APIC_OK;
 }
 
+int apic_schedule(apic_ctx* ctx, apic_sched* out) {
+    if (!ctx || !out) return fail(ctx, APIC_EINVAL, "null argument");
+    out->push_wg_per_cu = std::min(ctx->sched.push_wg_per_cu, push_resident_per_cu(ctx));
+    out->tile_log2 = ctx->sched.tile_log2;
+    out->sort_every = sort_every(ctx);
+    out->tuned = ctx->tuned ? 1 : 0;
+    return APIC_OK;
+}
+
 int apic_free(apic_ctx* ctx) {
     if (!ctx) return APIC_OK;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto& g : ctx->grains) free_grain(g);
-    for (auto& t : ctx->timers) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
-    }
-    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    free_ctx(ctx);
     delete ctx;
     return APIC_OK;
 }

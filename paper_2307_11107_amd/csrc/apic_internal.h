@@ -1,4 +1,15 @@
 // Internal structures of the APIC context and the launchers of its kernels.
+//
+// A context holds an ensemble of grains.  Every grain owns its grid, species,
+// particle buffers, multigrid hierarchy and counters; the kernels of one step
+// run over all grains at once from descriptor tables in device memory:
+//   PushTask  -- one per (grain, species): particle buffers and parameters,
+//                used by the push, deposit, injection and sort kernels;
+//   GrainDesc -- one per grain: node arrays of the field kernels;
+//   MGDesc    -- one per (level, grain): the multigrid level arrays.
+// All per-step state (slot counts, current buffer, injection accumulator, step
+// index, multigrid convergence) lives on the device, so a step is a fixed
+// launch sequence that is captured into HIP graphs and replayed.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,7 +44,7 @@ struct GrainParams {
     int tile_log2, ntx, ntiles; // sort tiles: 2^tile_log2 cells square, ntx per row
 };
 
-// Device counters of one grain (one allocation, zeroed at init).
+// Device counters and per-step state of one grain (one allocation, zeroed at init).
 struct DevCounters {
     int64_t n[APIC_MAX_SPECIES];              // particle slots in use (live + dead)
     uint64_t injected[APIC_MAX_SPECIES];
@@ -44,11 +55,14 @@ struct DevCounters {
     unsigned long long cursor;                // scratch for compaction
     uint32_t next_id[APIC_MAX_SPECIES];
     uint32_t overflow;                        // capacity exceeded (sticky)
-    uint32_t pad;
+    int32_t cur[APIC_MAX_SPECIES];            // current particle buffer (0/1)
+    uint32_t inj_id0[APIC_MAX_SPECIES];       // first id of this step's injection
+    uint32_t inj_tag;                         // Philox stream of this step's injection
+    uint64_t step;                            // injection steps taken
+    uint64_t inj_acc[APIC_MAX_SPECIES];       // injection accumulator, 2^-32 particles
+    int64_t inj_base[APIC_MAX_SPECIES];       // first slot of this step's injection
+    int64_t inj_new[APIC_MAX_SPECIES];        // particles drawn this step
     double F_el_sum;                          // sum of per-step electric force
-    double norm2;                             // scratch for residual norms
-    double norm2_b;
-    double norm2_e;
 };
 
 // Particle buffers of one species: SoA.  FP32 split: pos0 = int32 packed cell,
@@ -63,12 +77,75 @@ struct PBuf {
     uint32_t* id = nullptr;
 };
 
+// One (grain, species) of the ensemble, as the particle kernels see it.
+struct PushTask {
+    GrainParams gp;
+    SpeciesParams sp;
+    PBuf buf[2];                // double buffer; ctr->cur[s] selects the current one
+    const void* grad;           // float2 / double2 nodal (dphi/dx1, dphi/dx2)
+    void* dep;                  // float / double deposit sums of this species
+    DevCounters* ctr;
+    double* tally;              // [5][ns][n_bins]
+    unsigned long long* tally_count;
+    int* hist;                  // sort histograms, tile-major [ntiles][sort_blocks]
+    int* hist_off;              // their exclusive scan, + 1 total
+    int* seg;                   // scan partial sums
+    int64_t capacity;
+    uint64_t inj_inc;           // particles injected per step, 2^-32 units
+    int s, ns, grain, sort_blocks;
+};
+
+// One grain, as the field kernels see it.
+struct GrainDesc {
+    int n1, n2, nx, nodes, ns;
+    double inv_h1, inv_h2, h2, alpha, rhs_scale;    // rhs_scale = -1 / kappa^2
+    double phi_grain, phi_out;
+    double cw[APIC_MAX_SPECIES];                    // q w per species
+    double bnd2;                                    // |A_ib u_b|^2 (row-scaled), constant
+    const void* dep[APIC_MAX_SPECIES];
+    const double* vol;
+    double* rho;
+    double* u;                  // phi (finest multigrid level)
+    double* f;                  // right-hand side of the finest level
+    const double* diag;         // diagonal of the finest operator
+    void* grad;
+    DevCounters* ctr;
+};
+
+// One multigrid level of one grain.  n1 == 0: the grain has no such level.
+struct MGDesc {
+    int n1, n2, nx, nodes;
+    int coarsest;               // this is the grain's last level (dense solve)
+    int m;                      // nodes of the dense system (coarsest only)
+    const double* st;           // 9 stencil arrays [k * nodes + node]
+    double* u;
+    double* f;
+    const double* nn;           // finest level: second-neighbour axis couplings
+    const double* ss;
+    const double* inv;          // dense inverse (coarsest only)
+};
+
+// Convergence state of the in-step multigrid solves, per grain.
+struct MGState {
+    double r2;                  // |D^-1 r|^2 of the last check
+    double b2;                  // |D^-1 b|^2 of the current right-hand side
+    double last_r2;             // r2 of the last check
+    int done;                   // converged (or excluded from this solve)
+    int cycles;                 // cycles run in this solve
+};
+
+struct MGBatch {
+    int pending;                // grains not yet converged
+    int nan;                    // a residual was not finite
+    int max_cycles;             // largest cycles count of this solve
+    int pad;
+};
+
 struct MGLevel {
     int n1, n2, nx, nodes;
     double* st = nullptr;       // 9 stencil arrays [k * nodes + node], k = C,W,E,S,N,SW,SE,NW,NE
     double* u = nullptr;        // solution (level 0: phi) / correction
     double* f = nullptr;        // right-hand side
-    double* r = nullptr;        // residual
 };
 
 struct Grain {
@@ -79,23 +156,19 @@ struct Grain {
     int nodes = 0, ncells = 0;
     double V = 0, A_out = 0;
     std::vector<double> vol_host;
-    // injection fixed-point accumulators (units 2^-32 particles)
-    uint64_t inj_inc[APIC_MAX_SPECIES] = {0, 0};
-    uint64_t inj_acc[APIC_MAX_SPECIES] = {0, 0};
+    uint64_t inj_inc[APIC_MAX_SPECIES] = {0, 0};    // injection per step, 2^-32 units
     uint64_t step_index = 0;
     bool field_stale = true;
     int64_t capacity[APIC_MAX_SPECIES] = {0, 0};
-    int64_t host_slots[APIC_MAX_SPECIES] = {0, 0};  // upper bound of slots in use
     PBuf buf[APIC_MAX_SPECIES][2];
-    int cur[APIC_MAX_SPECIES] = {0, 0};
+    int cur[APIC_MAX_SPECIES] = {0, 0};             // host mirror of ctr->cur
+    int sort_blocks[APIC_MAX_SPECIES] = {0, 0};
     // device arrays
     DevCounters* ctr = nullptr;
     double* vol = nullptr;          // node volumes
     void* grad = nullptr;           // float2 / double2 nodal (dphi/dx1, dphi/dx2)
     void* dep[APIC_MAX_SPECIES] = {nullptr, nullptr};  // float / double deposit sums
     double* rho = nullptr;          // charge density of the last deposit
-    double* phi_prev = nullptr;     // potential of the previous step (initial-guess extrapolation)
-    bool have_prev = false;
     double* tally = nullptr;        // [5][ns][n_bins]: charge, pR, pZ, L, energy
     unsigned long long* tally_count = nullptr;   // [ns][n_bins]
     double* axis_nn = nullptr;      // level-0 second-neighbour coefficient on row i2 = 0
@@ -104,15 +177,31 @@ struct Grain {
     int coarse_nodes = 0;
     double bnd_norm2 = 0;           // |A_interior,boundary u_boundary|^2 (host)
     std::vector<MGLevel> mg;
-    hipGraphExec_t vcycle_exec = nullptr;   // captured V-cycle
-    // sort scratch
-    int* sort_count = nullptr;      // per-block tile histograms, ntiles * sort_blocks + 1
-    int* sort_offset = nullptr;     // their exclusive scan
-    void* scan_tmp = nullptr;
-    size_t scan_tmp_bytes = 0;
+    int* hist[APIC_MAX_SPECIES] = {nullptr, nullptr};
+    int* hist_off[APIC_MAX_SPECIES] = {nullptr, nullptr};
+    int* seg[APIC_MAX_SPECIES] = {nullptr, nullptr};
+};
+
+// Launch schedule of the particle kernels (chosen by the autotuner or defaults).
+struct Schedule {
+    int push_wg_per_cu = 8;     // persistent push workgroups per compute unit (capped at
+                                // what stays resident)
+    int tile_log2 = 3;          // sort tile edge, log2 cells (capped per grain)
+    int sort_every = 8;         // steps between sorts
+};
+
+// Progress of the autotuner across apic_step calls.
+struct TuneState {
+    int phase = 0, idx = 0;
+    float best = 1e30f;
+    int best_val = 0;
+    float sort_ms = 0;
+    std::vector<float> push_after;
 };
 
 struct TimerPair { hipEvent_t a, b; int kind; };
+
+enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_SORT, G_COUNT };
 
 }  // namespace apic
 
@@ -125,6 +214,32 @@ struct apic_ctx {
     int device = 0;
     int num_cus = 256;
     std::string err;
+    // ensemble tables (device) and their host copies
+    std::vector<apic::PushTask> tasks_h;
+    apic::PushTask* tasks = nullptr;
+    int ntasks = 0;
+    int64_t* chunk_prefix = nullptr;        // [ntasks + 1] chunks of the current push
+    std::vector<apic::GrainDesc> gdesc_h;
+    apic::GrainDesc* gdesc = nullptr;
+    int n_levels = 0;                       // deepest hierarchy of the ensemble
+    std::vector<apic::MGDesc> mgdesc_h;     // [level][grain]
+    apic::MGDesc* mgdesc = nullptr;
+    std::vector<int> lvl_max_n1, lvl_max_n2, lvl_max_nodes, lvl_lines_x2, lvl_max_m;
+    apic::MGState* mgs = nullptr;           // [grains]
+    double* norm_part = nullptr;            // [2][grains][blocks] partial norms (r, b)
+    apic::MGBatch* mgb = nullptr;
+    apic::MGBatch* mgb_host = nullptr;      // pinned
+    int max_inj_bound = 0;                  // largest per-step injection of any task
+    int max_ntiles = 0, max_sort_blocks = 0, max_segs = 0;
+    int max_nodes = 0, max_n1 = 0, max_n2 = 0;
+    int pred_cycles = 0;                    // cycles of the previous in-step solve
+    // schedule and graphs
+    apic::Schedule sched;
+    bool tuned = false;
+    bool tuning = false;                    // launches run eagerly while tuning
+    apic::TuneState tune;
+    hipGraphExec_t graph[apic::G_COUNT] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // profiling
     bool profiling = false;
     std::vector<apic::TimerPair> timers;   // recorded, not yet harvested
     std::vector<hipEvent_t> event_pool;
@@ -135,35 +250,34 @@ struct apic_ctx {
 namespace apic {
 
 // ------------------------------------------------------------------ launchers
-// particles.hip
-hipError_t launch_push(apic_ctx* ctx, Grain& g, int s);
-hipError_t launch_deposit_all(apic_ctx* ctx, Grain& g, int s);
-hipError_t launch_inject(apic_ctx* ctx, Grain& g, int s, int64_t n_new, uint32_t stream_tag);
+// particles.hip (ensemble-wide unless a grain is named)
+hipError_t launch_push(apic_ctx* ctx, bool deposit);
+hipError_t launch_deposit(apic_ctx* ctx);
+hipError_t launch_inject(apic_ctx* ctx, bool deposit);
+hipError_t launch_sort(apic_ctx* ctx);
 hipError_t launch_load(apic_ctx* ctx, Grain& g, int s, int64_t n);
 hipError_t launch_set_particles(apic_ctx* ctx, Grain& g, int s, int64_t n, const double* dx1,
                                 const double* dx2, const double* dvR, const double* dvZ,
                                 const double* dvT, int* d_bad);
 hipError_t launch_readback(apic_ctx* ctx, Grain& g, int s, int64_t n, double* dx1, double* dx2,
                            double* dvR, double* dvZ, double* dvT, int64_t* did);
-hipError_t launch_sort(apic_ctx* ctx, Grain& g, int s);
-hipError_t launch_add_slots(apic_ctx* ctx, Grain& g, int s, int64_t n_new);
 hipError_t launch_count_live(apic_ctx* ctx, Grain& g, int s, unsigned long long* out);
-size_t scan_temp_bytes(int n);
-int sort_blocks();
+int max_sort_blocks();
+int scan_seg_len();
+int push_chunk(bool split);
+int push_resident_per_cu(apic_ctx* ctx);
 
 // field.hip
 hipError_t launch_fill(apic_ctx* ctx, void* p, size_t bytes);
-hipError_t launch_rho(apic_ctx* ctx, Grain& g);
-hipError_t launch_rhs_from_rho(apic_ctx* ctx, Grain& g);
-hipError_t launch_gradient(apic_ctx* ctx, Grain& g);
-hipError_t launch_grain_force(apic_ctx* ctx, Grain& g);
-hipError_t launch_set_boundary(apic_ctx* ctx, Grain& g);
-hipError_t launch_extrapolate(apic_ctx* ctx, Grain& g);
-hipError_t launch_copy(apic_ctx* ctx, double* dst, const double* src, int n);
+hipError_t launch_clear_deposits(apic_ctx* ctx);
+hipError_t launch_rho_rhs(apic_ctx* ctx);
+hipError_t launch_rhs_from_rho(apic_ctx* ctx, int grain);
+hipError_t launch_gradient(apic_ctx* ctx);
+hipError_t launch_grain_force(apic_ctx* ctx);
+hipError_t launch_set_boundary(apic_ctx* ctx);
 
 // multigrid.hip
-hipError_t mg_vcycle(apic_ctx* ctx, Grain& g);
-hipError_t mg_residual_norm(apic_ctx* ctx, Grain& g, double* norm2_dev);
-hipError_t mg_rhs_norm(apic_ctx* ctx, Grain& g, double* norm2_dev);
+hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain);
+hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol);
 
 }  // namespace apic

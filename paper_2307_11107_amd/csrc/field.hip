@@ -1,12 +1,16 @@
-// Grid kernels beside the particle loop: charge density from the deposits
-// (weighting with the node volumes of eq. 5), the right-hand side of eq. (6),
-// the nodal derivatives of phi (second-order differences, used by eq. 10), and
-// the electric force on the grain from the surface field (Section 2: the field
-// on the conducting surface gives the surface charge and the electric force).
+// Grid kernels beside the particle loop, run for every grain of the ensemble at
+// once (blockIdx.y = grain): charge density from the deposits (weighting with
+// the node volumes of eq. 5), the right-hand side of eq. (6), the Dirichlet
+// values, the nodal derivatives of phi (second-order differences, used by
+// eq. 10), and the electric force on the grain from the surface field
+// (Section 2: the field on the conducting surface gives the surface charge and
+// the electric force).
 #include "apic_internal.h"
 #include "device_common.h"
 
 namespace apic {
+
+constexpr int FB = 256;
 
 __global__ void k_fill_u32(uint32_t* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -24,98 +28,95 @@ hipError_t launch_fill(apic_ctx* ctx, void* p, size_t bytes) {
     return hipGetLastError();
 }
 
-// rho = sum_s q_s w_s dep_s / V_node  (units e n0)
-template <typename D>
-__global__ void k_rho(int nodes, int ns, const D* __restrict__ dep0, const D* __restrict__ dep1,
-                      double c0, double c1, const double* __restrict__ vol, double* __restrict__ rho) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nodes) return;
-    double q = c0 * (double)dep0[i];
-    if (ns > 1) q += c1 * (double)dep1[i];
-    rho[i] = q / vol[i];
+static dim3 node_grid(apic_ctx* ctx) {
+    return dim3((ctx->max_nodes + FB - 1) / FB, (unsigned)ctx->grains.size());
 }
 
-hipError_t launch_rho(apic_ctx* ctx, Grain& g) {
-    const int grid = (g.nodes + 255) / 256;
-    const double c0 = g.sp[0].q * g.sp[0].w;
-    const double c1 = g.ns > 1 ? g.sp[1].q * g.sp[1].w : 0.0;
-    if (ctx->opts.precision == APIC_FP32_SPLIT)
-        hipLaunchKernelGGL(k_rho<float>, dim3(grid), dim3(256), 0, ctx->stream, g.nodes, g.ns,
-                           static_cast<const float*>(g.dep[0]),
-                           static_cast<const float*>(g.dep[g.ns > 1 ? 1 : 0]), c0, c1, g.vol, g.rho);
-    else
-        hipLaunchKernelGGL(k_rho<double>, dim3(grid), dim3(256), 0, ctx->stream, g.nodes, g.ns,
-                           static_cast<const double*>(g.dep[0]),
-                           static_cast<const double*>(g.dep[g.ns > 1 ? 1 : 0]), c0, c1, g.vol,
-                           g.rho);
+// deposit sums of every species to zero
+__global__ void __launch_bounds__(FB)
+k_clear_deposits(const GrainDesc* __restrict__ gd, int word_bytes) {
+    const GrainDesc& G = gd[blockIdx.y];
+    const int i = blockIdx.x * FB + threadIdx.x;
+    if (i >= G.nodes) return;
+    for (int s = 0; s < G.ns; ++s) {
+        if (word_bytes == 4) static_cast<float*>(const_cast<void*>(G.dep[s]))[i] = 0.f;
+        else static_cast<double*>(const_cast<void*>(G.dep[s]))[i] = 0.0;
+    }
+}
+
+hipError_t launch_clear_deposits(apic_ctx* ctx) {
+    hipLaunchKernelGGL(k_clear_deposits, node_grid(ctx), dim3(FB), 0, ctx->stream, ctx->gdesc,
+                       ctx->opts.precision == APIC_FP32_SPLIT ? 4 : 8);
     return hipGetLastError();
 }
 
-// f = -(1/kappa^2) rho at the unknown nodes (eq. 6 normalised); 0 on Dirichlet columns
-__global__ void k_rhs(int n1, int nx, int nodes, double scale, const double* __restrict__ rho,
-                      double* __restrict__ f) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nodes) return;
-    const int i1 = i % nx;
-    f[i] = (i1 == 0 || i1 == n1) ? 0.0 : scale * rho[i];
+// rho = sum_s q_s w_s dep_s / V_node (units e n0); f = -(1/kappa^2) rho at the
+// unknown nodes (eq. 6 normalised), 0 on the Dirichlet columns
+template <typename D>
+__global__ void __launch_bounds__(FB)
+k_rho_rhs(const GrainDesc* __restrict__ gd) {
+    const GrainDesc& G = gd[blockIdx.y];
+    const int i = blockIdx.x * FB + threadIdx.x;
+    if (i >= G.nodes) return;
+    double q = G.cw[0] * (double)static_cast<const D*>(G.dep[0])[i];
+    if (G.ns > 1) q += G.cw[1] * (double)static_cast<const D*>(G.dep[1])[i];
+    const double rho = q / G.vol[i];
+    G.rho[i] = rho;
+    const int i1 = i % G.nx;
+    G.f[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * rho;
 }
 
-hipError_t launch_rhs_from_rho(apic_ctx* ctx, Grain& g) {
-    const int grid = (g.nodes + 255) / 256;
-    hipLaunchKernelGGL(k_rhs, dim3(grid), dim3(256), 0, ctx->stream, g.gp.n1, g.gp.nx, g.nodes,
-                       -1.0 / (g.gp.kappa * g.gp.kappa), g.rho, g.mg[0].f);
+hipError_t launch_rho_rhs(apic_ctx* ctx) {
+    if (ctx->opts.precision == APIC_FP32_SPLIT)
+        hipLaunchKernelGGL(k_rho_rhs<float>, node_grid(ctx), dim3(FB), 0, ctx->stream, ctx->gdesc);
+    else
+        hipLaunchKernelGGL(k_rho_rhs<double>, node_grid(ctx), dim3(FB), 0, ctx->stream, ctx->gdesc);
+    return hipGetLastError();
+}
+
+// f from a given rho of one grain
+__global__ void __launch_bounds__(FB)
+k_rhs(const GrainDesc* __restrict__ gd, int grain) {
+    const GrainDesc& G = gd[grain];
+    const int i = blockIdx.x * FB + threadIdx.x;
+    if (i >= G.nodes) return;
+    const int i1 = i % G.nx;
+    G.f[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * G.rho[i];
+}
+
+hipError_t launch_rhs_from_rho(apic_ctx* ctx, int grain) {
+    const int nodes = ctx->grains[grain].nodes;
+    hipLaunchKernelGGL(k_rhs, dim3((nodes + FB - 1) / FB), dim3(FB), 0, ctx->stream, ctx->gdesc, grain);
     return hipGetLastError();
 }
 
 // Dirichlet values: phi = phi_grain on x1 = -1, phi_out on x1 = x1_out
-__global__ void k_set_boundary(int n1, int nx, int n2, double pg, double po, double* __restrict__ u) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > n2) return;
-    u[j * nx] = pg;
-    u[j * nx + n1] = po;
+__global__ void __launch_bounds__(FB)
+k_set_boundary(const GrainDesc* __restrict__ gd) {
+    const GrainDesc& G = gd[blockIdx.y];
+    const int j = blockIdx.x * FB + threadIdx.x;
+    if (j > G.n2) return;
+    G.u[j * G.nx] = G.phi_grain;
+    G.u[j * G.nx + G.n1] = G.phi_out;
 }
 
-hipError_t launch_set_boundary(apic_ctx* ctx, Grain& g) {
-    hipLaunchKernelGGL(k_set_boundary, dim3((g.gp.n2 + 256) / 256), dim3(256), 0, ctx->stream,
-                       g.gp.n1, g.gp.nx, g.gp.n2, g.cfg.phi_grain, g.cfg.phi_out, g.mg[0].u);
-    return hipGetLastError();
-}
-
-// Initial guess for the next solve: u <- 2 u - prev, prev <- old u (linear
-// extrapolation in time from the two previous potentials).
-__global__ void k_extrapolate(int nodes, double* __restrict__ u, double* __restrict__ prev) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nodes) return;
-    const double now = u[i];
-    u[i] = 2.0 * now - prev[i];
-    prev[i] = now;
-}
-
-hipError_t launch_extrapolate(apic_ctx* ctx, Grain& g) {
-    hipLaunchKernelGGL(k_extrapolate, dim3((g.nodes + 255) / 256), dim3(256), 0, ctx->stream, g.nodes,
-                       g.mg[0].u, g.phi_prev);
-    return hipGetLastError();
-}
-
-__global__ void k_copy(int n, double* __restrict__ dst, const double* __restrict__ src) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
-hipError_t launch_copy(apic_ctx* ctx, double* dst, const double* src, int n) {
-    hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, dst, src);
+hipError_t launch_set_boundary(apic_ctx* ctx) {
+    hipLaunchKernelGGL(k_set_boundary, dim3((ctx->max_n2 + FB) / FB, (unsigned)ctx->grains.size()),
+                       dim3(FB), 0, ctx->stream, ctx->gdesc);
     return hipGetLastError();
 }
 
 // Nodal (dphi/dx1, dphi/dx2): central inside, second-order one-sided on the edges.
 template <typename V>
-__global__ void k_gradient(int n1, int n2, double ih1, double ih2, const double* __restrict__ phi,
-                           V* __restrict__ grad) {
-    const int i1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i2 = blockIdx.y;
-    if (i1 > n1) return;
-    const int nx = n1 + 1;
-    const double* row = phi + (size_t)i2 * nx;
+__global__ void __launch_bounds__(FB)
+k_gradient(const GrainDesc* __restrict__ gd) {
+    const GrainDesc& G = gd[blockIdx.y];
+    const int idx = blockIdx.x * FB + threadIdx.x;
+    if (idx >= G.nodes) return;
+    const int n1 = G.n1, n2 = G.n2, nx = G.nx;
+    const int i2 = idx / nx, i1 = idx - i2 * nx;
+    const double ih1 = G.inv_h1, ih2 = G.inv_h2;
+    const double* row = G.u + (size_t)i2 * nx;
     double d1, d2;
     if (i1 == 0) d1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * ih1;
     else if (i1 == n1) d1 = (3.0 * row[n1] - 4.0 * row[n1 - 1] + row[n1 - 2]) * 0.5 * ih1;
@@ -126,26 +127,26 @@ __global__ void k_gradient(int n1, int n2, double ih1, double ih2, const double*
     V v;
     v.x = d1;
     v.y = d2;
-    grad[(size_t)i2 * nx + i1] = v;
+    static_cast<V*>(G.grad)[idx] = v;
 }
 
-hipError_t launch_gradient(apic_ctx* ctx, Grain& g) {
-    dim3 grid((g.gp.n1 + 256) / 256, g.gp.n2 + 1);
+hipError_t launch_gradient(apic_ctx* ctx) {
     if (ctx->opts.precision == APIC_FP32_SPLIT)
-        hipLaunchKernelGGL(k_gradient<float2>, grid, dim3(256), 0, ctx->stream, g.gp.n1, g.gp.n2,
-                           g.gp.inv_h1, g.gp.inv_h2, g.mg[0].u, static_cast<float2*>(g.grad));
+        hipLaunchKernelGGL(k_gradient<float2>, node_grid(ctx), dim3(FB), 0, ctx->stream, ctx->gdesc);
     else
-        hipLaunchKernelGGL(k_gradient<double2>, grid, dim3(256), 0, ctx->stream, g.gp.n1, g.gp.n2,
-                           g.gp.inv_h1, g.gp.inv_h2, g.mg[0].u, static_cast<double2*>(g.grad));
+        hipLaunchKernelGGL(k_gradient<double2>, node_grid(ctx), dim3(FB), 0, ctx->stream, ctx->gdesc);
     return hipGetLastError();
 }
 
 // Electric force on the grain, F_Z = integral over x1 = -1 of E_n^2 / 2 * n_Z dA
-// (Maxwell stress on a conductor), E_n = -|grad x1| dphi/dx1, trapezoid in x2.
-__global__ void k_grain_force(int n1, int n2, double alpha, double h2, double ih1,
-                              const double* __restrict__ phi, double* __restrict__ acc) {
-    __shared__ double red[256];
-    const int nx = n1 + 1;
+// (Maxwell stress on a conductor), E_n = -|grad x1| dphi/dx1, trapezoid in x2;
+// one workgroup per grain.
+__global__ void __launch_bounds__(FB)
+k_grain_force(const GrainDesc* __restrict__ gd) {
+    __shared__ double red[FB];
+    const GrainDesc& G = gd[blockIdx.x];
+    const int nx = G.nx, n2 = G.n2;
+    const double alpha = G.alpha, h2 = G.h2;
     double sum = 0.0;
     for (int j = threadIdx.x; j <= n2; j += blockDim.x) {
         const double x2 = -1.0 + j * h2;
@@ -153,8 +154,8 @@ __global__ void k_grain_force(int n1, int n2, double alpha, double h2, double ih
         const double s = sqrt(fmax(1.0 - x2 * x2, 0.0));
         const Metric<double> m = metric_at(r, x2, s, alpha);
         const double gn = sqrt(m.x1R * m.x1R + m.x1Z * m.x1Z);
-        const double* row = phi + (size_t)j * nx;
-        const double p1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * ih1;
+        const double* row = G.u + (size_t)j * nx;
+        const double p1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * G.inv_h1;
         const double En = -gn * p1;
         const double t = alpha / (r + 2.0 * alpha * x2);
         const double dA = 6.283185307179586 * r * r * sqrt(1.0 + (1.0 - x2 * x2) * t * t);
@@ -167,12 +168,12 @@ __global__ void k_grain_force(int n1, int n2, double alpha, double h2, double ih
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *acc += red[0] * h2;
+    if (threadIdx.x == 0) G.ctr->F_el_sum += red[0] * h2;
 }
 
-hipError_t launch_grain_force(apic_ctx* ctx, Grain& g) {
-    hipLaunchKernelGGL(k_grain_force, dim3(1), dim3(256), 0, ctx->stream, g.gp.n1, g.gp.n2,
-                       g.gp.alpha, g.gp.h2, g.gp.inv_h1, g.mg[0].u, &g.ctr->F_el_sum);
+hipError_t launch_grain_force(apic_ctx* ctx) {
+    hipLaunchKernelGGL(k_grain_force, dim3((unsigned)ctx->grains.size()), dim3(FB), 0, ctx->stream,
+                       ctx->gdesc);
     return hipGetLastError();
 }
 

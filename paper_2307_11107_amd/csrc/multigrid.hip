@@ -7,8 +7,13 @@
 // tridiagonal system solved in LDS by parallel cyclic reduction), and a dense
 // inverse on the coarsest grid (at most a few hundred nodes).  The operator's
 // anisotropy changes direction across the domain (the x1 coefficient falls like
-// r^-4), which is why both line directions are relaxed.  One V-cycle is
-// captured once into a HIP graph and replayed.
+// r^-4), which is why both line directions are relaxed.
+//
+// Every kernel works on one level of all grains of the ensemble at once
+// (blockIdx.y = grain, level arrays from the MGDesc table); grains whose
+// hierarchy is shallower, or whose solve has converged, leave at once.  A
+// V-cycle ends with the row-scaled residual norm and a convergence check on
+// the device, so cycles can be replayed from a graph without host reads.
 #include "apic_internal.h"
 
 namespace apic {
@@ -107,22 +112,39 @@ __device__ inline double apply_A(const StencilPtrs& p, const double* __restrict_
     return au;
 }
 
+__device__ inline bool level_active(const MGDesc& D, const MGState* ms) {
+    return D.n1 != 0 && !D.coarsest && !ms[blockIdx.y].done;
+}
+
+// line index of this workgroup: the lines are dealt out in eight contiguous
+// ranges, one per XCD (gridDim.x is a multiple of 8), so neighbouring lines,
+// which read each other's values, share an L2
+__device__ inline int xcd_line() {
+    const int per = gridDim.x >> 3;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
 template <int K, int NT>
 __global__ void __launch_bounds__(NT)
-k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
-           const double* __restrict__ nn, const double* __restrict__ ss, double* __restrict__ u,
-           const double* __restrict__ f) {
+k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
     extern __shared__ double lds[];
+    const MGDesc& D = lv[blockIdx.y];
+    if (!level_active(D, ms)) return;
+    const int n1 = D.n1, n2 = D.n2;
+    const int j = color + 2 * xcd_line();
+    if (j > n2) return;
     const int L = n1 - 1;
     double* a = lds;
     double* b = a + L;
     double* c = b + L;
     double* d = c + L;
-    const int j = color + 2 * blockIdx.x;
-    if (j > n2) return;
     const int nx = n1 + 1;
-    const StencilPtrs p = stencil_ptrs(st, nodes);
+    const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
+    const double* __restrict__ nn = D.nn;
+    const double* __restrict__ ss = D.ss;
+    double* __restrict__ u = D.u;
+    const double* __restrict__ f = D.f;
     for (int k = threadIdx.x; k < L; k += NT) {
         const int i = k + 1;
         const size_t o = (size_t)j * nx + i;
@@ -151,20 +173,25 @@ k_relax_x1(int n1, int n2, int color, const double* __restrict__ st, int nodes,
 // eliminated with the adjacent row so each line stays tridiagonal.
 template <int K, int LPB, int NT>
 __global__ void __launch_bounds__(NT)
-k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
-           const double* __restrict__ nn, const double* __restrict__ ss, double* __restrict__ u,
-           const double* __restrict__ f) {
+k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
     extern __shared__ double lds[];
+    const MGDesc& D = lv[blockIdx.y];
+    if (!level_active(D, ms)) return;
+    const int n1 = D.n1, n2 = D.n2;
+    const int i0 = 1 + color + 2 * LPB * xcd_line();
+    if (i0 > n1 - 1) return;
     const int L = n2 + 1;
     const int total = LPB * L;
     double* a = lds;
     double* b = a + total;
     double* c = b + total;
     double* d = c + total;
-    const int i0 = 1 + color + 2 * LPB * blockIdx.x;
-    if (i0 > n1 - 1) return;
     const int nx = n1 + 1;
-    const StencilPtrs p = stencil_ptrs(st, nodes);
+    const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
+    const double* __restrict__ nn = D.nn;
+    const double* __restrict__ ss = D.ss;
+    double* __restrict__ u = D.u;
+    const double* __restrict__ f = D.f;
     for (int q = threadIdx.x; q < total; q += NT) {
         const int m = q % LPB, j = q / LPB;
         const int i = i0 + 2 * m;
@@ -217,56 +244,134 @@ k_relax_x2(int n1, int n2, int color, const double* __restrict__ st, int nodes,
     }
 }
 
-// Block sum of a per-thread value, one atomic per block.
-__device__ inline void block_sum_add(double v, double* dst) {
+// Block sum of a per-thread value (fixed order), written by thread 0.
+__device__ inline double block_sum(double v) {
     __shared__ double red[MG_BLOCK / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
+    double t = 0.0;
+    if (threadIdx.x == 0)
         for (int w = 0; w < MG_BLOCK / 64; ++w) t += red[w];
-        atomicAdd(dst, t);
-    }
+    __syncthreads();
+    return t;
 }
 
 // |D^-1 (f - A u)|^2 over the unknown nodes of the finest level (D = diagonal
 // of A): the operator's rows differ in scale by ~r^4, and the row-scaled norm
-// weighs every node alike.
+// weighs every node alike.  One partial sum per workgroup, part[grain][block];
+// the check adds them in a fixed order, so a solve is reproducible bit for bit.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_residual_norm(int n1, int n2, const double* __restrict__ st, int nodes,
-                const double* __restrict__ nn, const double* __restrict__ ss,
-                const double* __restrict__ u, const double* __restrict__ f, double* norm2) {
-    const int nx = n1 + 1;
+k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part) {
+    const MGDesc& D = lv[blockIdx.y];
+    double* out = part + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (D.n1 == 0 || ms[blockIdx.y].done || (int)(blockIdx.x * MG_BLOCK) >= D.nodes) {
+        if (threadIdx.x == 0) *out = 0.0;
+        return;
+    }
+    const int n1 = D.n1, n2 = D.n2, nx = n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     double rr = 0.0;
-    if (idx < nodes) {
+    if (idx < D.nodes) {
         const int j = idx / nx, i = idx - j * nx;
         if (i > 0 && i < n1) {
-            const StencilPtrs p = stencil_ptrs(st, nodes);
-            const double q = (f[idx] - apply_A(p, nn, ss, u, n2, nx, j, i)) / p.C[idx];
+            const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
+            const double q = (D.f[idx] - apply_A(p, D.nn, D.ss, D.u, n2, nx, j, i)) / p.C[idx];
             rr = q * q;
         }
     }
-    block_sum_add(rr, norm2);
+    const double t = block_sum(rr);
+    if (threadIdx.x == 0) *out = t;
 }
 
-// |D^-1 f|^2 over the unknown nodes
+// |D^-1 f|^2 over the unknown nodes, partial sums as above
 __global__ void __launch_bounds__(MG_BLOCK)
-k_rhs_norm(int n1, int nodes, const double* __restrict__ diag, const double* __restrict__ f,
-           double* norm2) {
-    const int nx = n1 + 1;
+k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part) {
+    const MGDesc& D = lv[blockIdx.y];
+    double* out = part + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (D.n1 == 0 || ms[blockIdx.y].done || (int)(blockIdx.x * MG_BLOCK) >= D.nodes) {
+        if (threadIdx.x == 0) *out = 0.0;
+        return;
+    }
+    const int nx = D.n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     double v = 0.0;
-    if (idx < nodes) {
+    if (idx < D.nodes) {
         const int i = idx % nx;
-        if (i > 0 && i < n1) {
-            const double q = f[idx] / diag[idx];
+        if (i > 0 && i < D.n1) {
+            const double q = D.f[idx] / D.st[ST_C * (size_t)D.nodes + idx];
             v = q * q;
         }
     }
-    block_sum_add(v, norm2);
+    const double t = block_sum(v);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// Start of a solve: grains other than `only` (if >= 0) are excluded from it.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_mg_reset(MGState* __restrict__ ms, int ngrains, int only) {
+    for (int g = threadIdx.x; g < ngrains; g += MG_BLOCK) {
+        ms[g].r2 = 0.0;
+        ms[g].b2 = 0.0;
+        ms[g].cycles = 0;
+        ms[g].done = (only >= 0 && g != only) ? 1 : 0;
+    }
+}
+
+// Sum of nb partial sums in a fixed order (one workgroup).
+__device__ inline double sum_parts(const double* __restrict__ p, int nb) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += MG_BLOCK) v += p[k];
+    return block_sum(v);
+}
+
+// Convergence check after the residual norm: a grain is done once
+// |D^-1 r| <= tol |D^-1 b| (b with the boundary coupling) or when its residual
+// is not finite; count_cycle marks the check that ends a V-cycle; with_b also
+// takes |D^-1 b|^2 from its partial sums (start of a solve).  One workgroup.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_mg_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int ngrains, int nb,
+           const double* __restrict__ part_r, const double* __restrict__ part_b, double tol2,
+           int count_cycle, MGBatch* __restrict__ mb) {
+    __shared__ int s_pending, s_nan, s_max;
+    if (threadIdx.x == 0) {
+        s_pending = 0;
+        s_nan = mb->nan;
+        s_max = 0;
+    }
+    __syncthreads();
+    for (int g = 0; g < ngrains; ++g) {
+        MGState& m = ms[g];
+        const int was_done = m.done;
+        double r2 = 0.0, b2 = 0.0;
+        if (!was_done) {
+            r2 = sum_parts(part_r + (size_t)g * nb, nb);
+            if (part_b) b2 = sum_parts(part_b + (size_t)g * nb, nb);
+        }
+        if (threadIdx.x == 0) {
+            if (!was_done) {
+                if (part_b) m.b2 = b2;
+                m.r2 = r2;
+                m.last_r2 = r2;
+                if (count_cycle) m.cycles += 1;
+                if (!(r2 == r2) || !(m.b2 == m.b2)) {
+                    s_nan = 1;
+                    m.done = 1;
+                } else if (r2 <= tol2 * (m.b2 + gd[g].bnd2)) {
+                    m.done = 1;
+                }
+            }
+            s_pending += m.done ? 0 : 1;
+            s_max = max(s_max, m.cycles);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        mb->pending = s_pending;
+        mb->nan = s_nan;
+        mb->max_cycles = s_max;
+    }
 }
 
 // Coarse right-hand side fc = P^T (f - A u) / 4 on the coarse unknowns, the
@@ -274,20 +379,22 @@ k_rhs_norm(int n1, int nodes, const double* __restrict__ diag, const double* __r
 // grid); fc = 0 on the coarse Dirichlet columns; the coarse correction uc is
 // cleared.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_restrict_residual(int n1f, int n2f, const double* __restrict__ st, int nodes_f,
-                    const double* __restrict__ nn, const double* __restrict__ ss,
-                    const double* __restrict__ u, const double* __restrict__ f, int n1c, int n2c,
-                    double* __restrict__ fc, double* __restrict__ uc) {
-    const int nxc = n1c + 1, nxf = n1f + 1;
+k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
+                    const MGState* __restrict__ ms) {
+    const MGDesc& F = fine[blockIdx.y];
+    const MGDesc& C = coarse[blockIdx.y];
+    if (C.n1 == 0 || !level_active(F, ms)) return;
+    const int n1c = C.n1, nxc = n1c + 1;
+    const int n2f = F.n2, nxf = F.n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
-    if (idx >= nxc * (n2c + 1)) return;
-    uc[idx] = 0.0;
+    if (idx >= C.nodes) return;
+    C.u[idx] = 0.0;
     const int J = idx / nxc, I = idx - J * nxc;
     if (I == 0 || I == n1c) {
-        fc[idx] = 0.0;
+        C.f[idx] = 0.0;
         return;
     }
-    const StencilPtrs p = stencil_ptrs(st, nodes_f);
+    const StencilPtrs p = stencil_ptrs(F.st, F.nodes);
     double acc = 0.0;
     for (int dj = -1; dj <= 1; ++dj) {
         const int j = 2 * J + dj;
@@ -296,183 +403,192 @@ k_restrict_residual(int n1f, int n2f, const double* __restrict__ st, int nodes_f
         for (int di = -1; di <= 1; ++di) {
             const int i = 2 * I + di;      // 1 <= i <= n1f - 1
             const double wi = di == 0 ? 1.0 : 0.5;
-            const double r = f[(size_t)j * nxf + i] - apply_A(p, nn, ss, u, n2f, nxf, j, i);
+            const double r = F.f[(size_t)j * nxf + i] - apply_A(p, F.nn, F.ss, F.u, n2f, nxf, j, i);
             acc += wj * wi * r;
         }
     }
-    fc[idx] = 0.25 * acc;
+    C.f[idx] = 0.25 * acc;
 }
 
 // fine u += P uc (bilinear) on the fine unknowns
 __global__ void __launch_bounds__(MG_BLOCK)
-k_prolong_add(int n1f, int n2f, int n1c, const double* __restrict__ uc, double* __restrict__ uf) {
-    const int nxc = n1c + 1, nxf = n1f + 1;
+k_prolong_add(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
+              const MGState* __restrict__ ms) {
+    const MGDesc& F = fine[blockIdx.y];
+    const MGDesc& C = coarse[blockIdx.y];
+    if (C.n1 == 0 || !level_active(F, ms)) return;
+    const int nxc = C.n1 + 1, n1f = F.n1, nxf = n1f + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
-    if (idx >= nxf * (n2f + 1)) return;
+    if (idx >= F.nodes) return;
     const int j = idx / nxf, i = idx - j * nxf;
     if (i == 0 || i == n1f) return;
     const int J0 = j >> 1, I0 = i >> 1;
     const int J1 = (j & 1) ? J0 + 1 : J0;
     const int I1 = (i & 1) ? I0 + 1 : I0;
+    const double* uc = C.u;
     const double v = 0.25 * (uc[(size_t)J0 * nxc + I0] + uc[(size_t)J0 * nxc + I1] +
                              uc[(size_t)J1 * nxc + I0] + uc[(size_t)J1 * nxc + I1]);
-    uf[idx] += v;
+    F.u[idx] += v;
 }
 
-// coarsest grid: u = A^-1 f (dense inverse with identity Dirichlet rows), one
-// wave per row
+// Dense solve on a grain's coarsest level: u = A^-1 rhs with rhs = f on the
+// unknowns and rhs = u on the Dirichlet columns (identity rows of A), so the
+// same kernel serves a correction level (u = 0 there) and a grid that is
+// itself small enough; one wave per unknown row.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_coarse_solve(int m, const double* __restrict__ inv, const double* __restrict__ f,
-               double* __restrict__ u) {
+k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
+    const MGDesc& D = lv[blockIdx.y];
+    if (D.n1 == 0 || !D.coarsest || ms[blockIdx.y].done) return;
+    const int m = D.m, nx = D.n1 + 1;
     const int row = blockIdx.x * (MG_BLOCK / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= m) return;
-    const double* a = inv + (size_t)row * m;
+    const int ri = row % nx;
+    if (ri == 0 || ri == D.n1) return;
+    const double* a = D.inv + (size_t)row * m;
     double acc = 0.0;
-    for (int k = lane; k < m; k += 64) acc += a[k] * f[k];
+    for (int k = lane; k < m; k += 64) {
+        const int i = k % nx;
+        acc += a[k] * ((i == 0 || i == D.n1) ? D.u[k] : D.f[k]);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) u[row] = acc;
+    if (lane == 0) D.u[row] = acc;
 }
 
+// ------------------------------------------------------------------ launches
 // Line-solve launches.  A line of L unknowns gets NT = 512 threads when it is
 // long (fewer equations per thread, shorter PCR critical path), else 256; the
 // x2 sweeps group LPB neighbouring lines of one colour per workgroup while
 // that still leaves at least two workgroups per compute unit.
-template <int K, int NT>
-static void relax_x1_launch(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
-    const size_t lds = 4 * sizeof(double) * (size_t)(L.n1 - 1);
-    const int lines = (L.n2 + 1 - color + 1) / 2;
-    hipLaunchKernelGGL((k_relax_x1<K, NT>), dim3(lines), dim3(NT), lds, ctx->stream, L.n1, L.n2,
-                       color, L.st, L.nodes, nn, ss, L.u, L.f);
-}
-
-template <int K, int LPB, int NT>
-static void relax_x2_launch(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
-    const size_t lds = 4 * sizeof(double) * (size_t)LPB * (L.n2 + 1);
-    const int lines = (L.n1 - 1 - color + 1) / 2;
-    if (lines <= 0) return;
-    const int blocks = (lines + LPB - 1) / LPB;
-    hipLaunchKernelGGL((k_relax_x2<K, LPB, NT>), dim3(blocks), dim3(NT), lds, ctx->stream, L.n1,
-                       L.n2, color, L.st, L.nodes, nn, ss, L.u, L.f);
-}
+static int round8(int x) { return (x + 7) / 8 * 8; }
 
 static int pcr_k(int total, int nt) {
     const int k = (total + nt - 1) / nt;
     return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8;
 }
 
+template <int K, int NT>
+static void relax_x1_launch(apic_ctx* ctx, int l, int color) {
+    const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
+    const size_t lds = 4 * sizeof(double) * (size_t)(mn1 - 1);
+    const int lines = (mn2 + 1 - color + 1) / 2;
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL((k_relax_x1<K, NT>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
+                       ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
+}
+
+template <int K, int LPB, int NT>
+static void relax_x2_launch(apic_ctx* ctx, int l, int color) {
+    const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
+    const size_t lds = 4 * sizeof(double) * (size_t)LPB * (mn2 + 1);
+    const int lines = (mn1 - 1 - color + 1) / 2;
+    if (lines <= 0) return;
+    const int blocks = (lines + LPB - 1) / LPB;
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL((k_relax_x2<K, LPB, NT>), dim3(round8(blocks), G), dim3(NT), lds, ctx->stream,
+                       ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
+}
+
 template <int NT>
-static void relax_x1_k(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
-    switch (pcr_k(L.n1 - 1, NT)) {
-        case 1: relax_x1_launch<1, NT>(ctx, L, nn, ss, color); break;
-        case 2: relax_x1_launch<2, NT>(ctx, L, nn, ss, color); break;
-        case 4: relax_x1_launch<4, NT>(ctx, L, nn, ss, color); break;
-        default: relax_x1_launch<8, NT>(ctx, L, nn, ss, color); break;
+static void relax_x1_k(apic_ctx* ctx, int l, int color) {
+    switch (pcr_k(ctx->lvl_max_n1[l] - 1, NT)) {
+        case 1: relax_x1_launch<1, NT>(ctx, l, color); break;
+        case 2: relax_x1_launch<2, NT>(ctx, l, color); break;
+        case 4: relax_x1_launch<4, NT>(ctx, l, color); break;
+        default: relax_x1_launch<8, NT>(ctx, l, color); break;
     }
 }
 
 template <int LPB, int NT>
-static void relax_x2_k(apic_ctx* ctx, const MGLevel& L, const double* nn, const double* ss, int color) {
-    switch (pcr_k(LPB * (L.n2 + 1), NT)) {
-        case 1: relax_x2_launch<1, LPB, NT>(ctx, L, nn, ss, color); break;
-        case 2: relax_x2_launch<2, LPB, NT>(ctx, L, nn, ss, color); break;
-        case 4: relax_x2_launch<4, LPB, NT>(ctx, L, nn, ss, color); break;
-        default: relax_x2_launch<8, LPB, NT>(ctx, L, nn, ss, color); break;
+static void relax_x2_k(apic_ctx* ctx, int l, int color) {
+    switch (pcr_k(LPB * (ctx->lvl_max_n2[l] + 1), NT)) {
+        case 1: relax_x2_launch<1, LPB, NT>(ctx, l, color); break;
+        case 2: relax_x2_launch<2, LPB, NT>(ctx, l, color); break;
+        case 4: relax_x2_launch<4, LPB, NT>(ctx, l, color); break;
+        default: relax_x2_launch<8, LPB, NT>(ctx, l, color); break;
     }
 }
 
-static void relax(apic_ctx* ctx, Grain& g, int l) {
-    const MGLevel& L = g.mg[l];
-    const double* nn = l == 0 ? g.axis_nn : nullptr;
-    const double* ss = l == 0 ? g.axis_ss : nullptr;
+static void relax(apic_ctx* ctx, int l) {
+    const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     for (int color = 0; color < 2; ++color) {
-        if (L.n1 - 1 > 512) relax_x1_k<512>(ctx, L, nn, ss, color);
-        else relax_x1_k<256>(ctx, L, nn, ss, color);
+        if (mn1 - 1 > 512) relax_x1_k<512>(ctx, l, color);
+        else relax_x1_k<256>(ctx, l, color);
     }
-    const int Lx2 = L.n2 + 1;
-    const int lines = (L.n1 - 1 + 1) / 2;
+    const int Lx2 = mn2 + 1;
+    const int lines = ctx->lvl_lines_x2[l];   // x2 lines of one colour, summed over grains
     int lpb = 4;
     while (lpb > 1 && (4 * sizeof(double) * (size_t)lpb * Lx2 > 65536 || lpb * Lx2 > 8 * 256 ||
-                       (lines + lpb - 1) / lpb < 2 * ctx->num_cus))
+                       lines / lpb < 2 * ctx->num_cus))
         lpb >>= 1;
     for (int color = 0; color < 2; ++color) {
-        if (lpb == 4) relax_x2_k<4, 256>(ctx, L, nn, ss, color);
-        else if (lpb == 2) relax_x2_k<2, 256>(ctx, L, nn, ss, color);
-        else if (Lx2 > 512) relax_x2_k<1, 512>(ctx, L, nn, ss, color);
-        else relax_x2_k<1, 256>(ctx, L, nn, ss, color);
+        if (lpb == 4) relax_x2_k<4, 256>(ctx, l, color);
+        else if (lpb == 2) relax_x2_k<2, 256>(ctx, l, color);
+        else if (Lx2 > 512) relax_x2_k<1, 512>(ctx, l, color);
+        else relax_x2_k<1, 256>(ctx, l, color);
     }
 }
 
-static void vcycle_launches(apic_ctx* ctx, Grain& g) {
-    const int nl = (int)g.mg.size();
+static void coarse_solve(apic_ctx* ctx, int l) {
+    const int G = (int)ctx->grains.size();
+    const int m = ctx->lvl_max_m[l];
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_coarse_solve, dim3((m + MG_BLOCK / 64 - 1) / (MG_BLOCK / 64), G),
+                       dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgs);
+}
+
+static int norm_blocks(apic_ctx* ctx) { return (ctx->lvl_max_nodes[0] + MG_BLOCK - 1) / MG_BLOCK; }
+
+static void residual_norm(apic_ctx* ctx) {
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL(k_residual_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream,
+                       ctx->mgdesc, ctx->mgs, ctx->norm_part);
+}
+
+static void check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
+    const int G = (int)ctx->grains.size();
+    const int nb = norm_blocks(ctx);
+    hipLaunchKernelGGL(k_mg_check, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, ctx->gdesc, G, nb,
+                       ctx->norm_part, with_b ? ctx->norm_part + (size_t)G * nb : nullptr, tol * tol,
+                       count_cycle, ctx->mgb);
+}
+
+// Start of a solve on the current right-hand side (Dirichlet values already
+// set): |D^-1 b|^2, the initial residual, and the check (grains that already
+// meet the tolerance are done).
+hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain) {
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, G, only_grain);
+    hipLaunchKernelGGL(k_rhs_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
+                       ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
+    residual_norm(ctx);
+    check(ctx, tol, 0, true);
+    return hipGetLastError();
+}
+
+// One V-cycle of every grain not yet done, then the residual norm and the check.
+hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
+    const int G = (int)ctx->grains.size();
+    const int nl = ctx->n_levels;
+    coarse_solve(ctx, 0);
     for (int l = 0; l + 1 < nl; ++l) {
-        MGLevel& F = g.mg[l];
-        MGLevel& C = g.mg[l + 1];
-        relax(ctx, g, l);
-        hipLaunchKernelGGL(k_restrict_residual, dim3((C.nodes + MG_BLOCK - 1) / MG_BLOCK),
-                           dim3(MG_BLOCK), 0, ctx->stream, F.n1, F.n2, F.st, F.nodes,
-                           l == 0 ? g.axis_nn : nullptr, l == 0 ? g.axis_ss : nullptr, F.u, F.f,
-                           C.n1, C.n2, C.f, C.u);
+        relax(ctx, l);
+        const int cn = ctx->lvl_max_nodes[l + 1];
+        hipLaunchKernelGGL(k_restrict_residual, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
+                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
+                           ctx->mgs);
+        coarse_solve(ctx, l + 1);
     }
-    MGLevel& B = g.mg[nl - 1];
-    hipLaunchKernelGGL(k_coarse_solve, dim3((B.nodes + MG_BLOCK / 64 - 1) / (MG_BLOCK / 64)),
-                       dim3(MG_BLOCK), 0, ctx->stream, B.nodes, g.coarse_inv, B.f, B.u);
     for (int l = nl - 2; l >= 0; --l) {
-        MGLevel& F = g.mg[l];
-        MGLevel& C = g.mg[l + 1];
-        hipLaunchKernelGGL(k_prolong_add, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK),
-                           0, ctx->stream, F.n1, F.n2, C.n1, C.u, F.u);
-        relax(ctx, g, l);
+        const int fn = ctx->lvl_max_nodes[l];
+        hipLaunchKernelGGL(k_prolong_add, dim3((fn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
+                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
+                           ctx->mgs);
+        relax(ctx, l);
     }
-    // row-scaled residual norm of the result
-    MGLevel& F = g.mg[0];
-    (void)launch_fill(ctx, &g.ctr->norm2, sizeof(double));
-    hipLaunchKernelGGL(k_residual_norm, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                       ctx->stream, F.n1, F.n2, F.st, F.nodes, g.axis_nn, g.axis_ss, F.u, F.f,
-                       &g.ctr->norm2);
-}
-
-// One V-cycle followed by the residual norm into ctr->norm2.  The launch
-// sequence is captured once into a graph (when the stream can be captured)
-// and replayed afterwards.
-hipError_t mg_vcycle(apic_ctx* ctx, Grain& g) {
-    if (!g.vcycle_exec && ctx->graphs) {
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            vcycle_launches(ctx, g);
-            e = hipStreamEndCapture(ctx->stream, &graph);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&g.vcycle_exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            g.vcycle_exec = nullptr;
-            ctx->graphs = false;
-        }
-    }
-    if (g.vcycle_exec) return hipGraphLaunch(g.vcycle_exec, ctx->stream);
-    vcycle_launches(ctx, g);
-    return hipGetLastError();
-}
-
-hipError_t mg_residual_norm(apic_ctx* ctx, Grain& g, double* norm2_dev) {
-    MGLevel& F = g.mg[0];
-    hipError_t e = launch_fill(ctx, norm2_dev, sizeof(double));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_residual_norm, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                       ctx->stream, F.n1, F.n2, F.st, F.nodes, g.axis_nn, g.axis_ss, F.u, F.f,
-                       norm2_dev);
-    return hipGetLastError();
-}
-
-hipError_t mg_rhs_norm(apic_ctx* ctx, Grain& g, double* norm2_dev) {
-    MGLevel& F = g.mg[0];
-    hipError_t e = launch_fill(ctx, norm2_dev, sizeof(double));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rhs_norm, dim3((F.nodes + MG_BLOCK - 1) / MG_BLOCK), dim3(MG_BLOCK), 0,
-                       ctx->stream, F.n1, F.nodes, F.st + ST_C * (size_t)F.nodes, F.f, norm2_dev);
+    residual_norm(ctx);
+    check(ctx, tol, 1, false);
     return hipGetLastError();
 }
 

@@ -26,8 +26,7 @@
 #include "apic_internal.h"
 #include "device_common.h"
 
-#include <hipcub/hipcub.hpp>
-
+#include <algorithm>
 #include <type_traits>
 
 namespace apic {
@@ -57,11 +56,17 @@ __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
 // Bisection on x1 + 1 along the chord P(t) = (R + t dX, t dY, Z + t dZ) between
 // t = 0 (outside) and t_in (inside); tallies at the impact point with the
 // velocity rotated into the impact point's meridional plane.
+// The impact parameters come as scalars (no struct by reference), so a caller's
+// parameter structs can stay in registers.
+struct ImpactSpecies {
+    double q, m, w, e_bind;
+};
+
 template <typename T>
-__device__ __attribute__((noinline)) void tally_impact(const GrainParams& gp, const SpeciesParams& sp, int s, int ns,
+__device__ __attribute__((noinline)) void tally_impact(double alpha_d, int n_bins, ImpactSpecies sp, int s, int ns,
                              T R, T Z, T dX, T dY, T dZ, T t_in, T vR, T vZ, T vT,
                              double* tally, unsigned long long* tally_count, int iters) {
-    const T alpha = (T)gp.alpha;
+    const T alpha = (T)alpha_d;
     T lo = 0, hi = t_in;
     for (int it = 0; it < iters; ++it) {
         const T mid = T(0.5) * (lo + hi);
@@ -76,15 +81,15 @@ __device__ __attribute__((noinline)) void tally_impact(const GrainParams& gp, co
     const T Ri = sqrt(X * X + Y * Y);
     const T ri = sqrt(Ri * Ri + Zi * Zi);
     const T x2 = Zi / ri;
-    int b = (int)floor((x2 + T(1)) * T(0.5) * (T)gp.n_bins);
-    b = b < 0 ? 0 : (b >= gp.n_bins ? gp.n_bins - 1 : b);
+    int b = (int)floor((x2 + T(1)) * T(0.5) * (T)n_bins);
+    b = b < 0 ? 0 : (b >= n_bins ? n_bins - 1 : b);
     T c = 1, sn = 0;
     if (Ri > T(0)) { c = X / Ri; sn = Y / Ri; }
     const double vRi = (double)(c * vR + sn * vT);
     const double vTi = (double)(-sn * vR + c * vT);
     const double v2 = (double)vR * vR + (double)vZ * vZ + (double)vT * vT;
-    const size_t stride = (size_t)ns * gp.n_bins;
-    const size_t o = (size_t)s * gp.n_bins + b;
+    const size_t stride = (size_t)ns * n_bins;
+    const size_t o = (size_t)s * n_bins + b;
     atomic_add_f64(&tally[o], sp.q * sp.w);
     atomic_add_f64(&tally[stride + o], sp.m * sp.w * vRi);
     atomic_add_f64(&tally[2 * stride + o], sp.m * sp.w * (double)vZ);
@@ -146,21 +151,45 @@ __device__ inline SplitConsts split_consts(const GrainParams& gp, const SpeciesP
     return k;
 }
 
+struct SplitState {
+    int32_t c;
+    float f1, f2, vR, vZ, vT;
+};
+
+__device__ inline SplitState load_split(const PBuf& b, int64_t p) {
+    SplitState q;
+    q.c = static_cast<const int32_t*>(b.pos0)[p];
+    q.f1 = static_cast<const float*>(b.pos1)[p];
+    q.f2 = static_cast<const float*>(b.pos2)[p];
+    q.vR = static_cast<const float*>(b.vR)[p];
+    q.vZ = static_cast<const float*>(b.vZ)[p];
+    q.vT = static_cast<const float*>(b.vT)[p];
+    return q;
+}
+
+__device__ inline void set_dead(SplitState& q) { q.c = DEAD; }
+__device__ inline bool is_dead(const SplitState& q) { return q.c < 0; }
+
+// Advances one particle given its loaded state q; writes slot p of b.
 __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams& sp,
                                      const SplitConsts& K, int s, int ns, int64_t p,
-                                     int32_t* __restrict__ cell, float* __restrict__ f1a,
-                                     float* __restrict__ f2a, float* __restrict__ vRa,
-                                     float* __restrict__ vZa, float* __restrict__ vTa,
+                                     const SplitState& q, const PBuf& b,
                                      const float2* __restrict__ grad, double* __restrict__ tally,
                                      unsigned long long* __restrict__ tally_count, int& i1n,
                                      int& i2n, float& f1n, float& f2n) {
-    const int32_t c = cell[p];
+    const int32_t c = q.c;
     if (c < 0) return -1;
+    int32_t* __restrict__ cell = static_cast<int32_t*>(b.pos0);
+    float* __restrict__ f1a = static_cast<float*>(b.pos1);
+    float* __restrict__ f2a = static_cast<float*>(b.pos2);
+    float* __restrict__ vRa = static_cast<float*>(b.vR);
+    float* __restrict__ vZa = static_cast<float*>(b.vZ);
+    float* __restrict__ vTa = static_cast<float*>(b.vT);
     const int n1 = K.n1, n2 = K.n2, nx = K.nx;
     const float alpha = K.alpha, h1 = K.h1, h2 = K.h2, qmh = K.qmh, step = K.step;
     const int i1 = cell_i1(c), i2 = cell_i2(c);
-    const float f1 = f1a[p], f2 = f2a[p];
-    float vR = vRa[p], vZ = vZa[p], vT = vTa[p];
+    const float f1 = q.f1, f2 = q.f2;
+    float vR = q.vR, vZ = q.vZ, vT = q.vT;
 
     // gather (bilinear in the logical coordinates)
     const int idx = i2 * nx + i1;
@@ -262,7 +291,8 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
     const float tmid = chord_inside<float>(gp, R, Z, dX, dY, dZ);
     if (i1n < 0 || tmid > 0.f) {
         const float t_in = tmid > 0.f ? tmid : 1.f;
-        tally_impact<float>(gp, sp, s, ns, R, Z, dX, dY, dZ, t_in, vR, vZ, vT, tally, tally_count, 24);
+        tally_impact<float>(gp.alpha, gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
+                            dY, dZ, t_in, vR, vZ, vT, tally, tally_count, 24);
         cell[p] = DEAD;
         return 1;
     }
@@ -322,7 +352,8 @@ __device__ inline int drift_and_bound64(const GrainParams& gp, const SpeciesPara
     x1n = x1_of(rn, x2n, gp.alpha);
     const double tmid = chord_inside<double>(gp, R, Z, dX, dY, dZ);
     if (!(x1n > -1.0) || tmid > 0.0) {
-        tally_impact<double>(gp, sp, s, ns, R, Z, dX, dY, dZ, tmid > 0.0 ? tmid : 1.0, vR, vZ,
+        tally_impact<double>(gp.alpha, gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
+                             dY, dZ, tmid > 0.0 ? tmid : 1.0, vR, vZ,
                              vT, tally, tally_count, 48);
         return 1;
     }
@@ -331,19 +362,39 @@ __device__ inline int drift_and_bound64(const GrainParams& gp, const SpeciesPara
 }
 
 // One particle of the FP64 plain form; same return convention as the split form.
+struct PlainState {
+    double x1, x2, vR, vZ, vT;
+};
+
+__device__ inline PlainState load_plain(const PBuf& b, int64_t p) {
+    PlainState q;
+    q.x1 = static_cast<const double*>(b.pos1)[p];
+    q.x2 = static_cast<const double*>(b.pos2)[p];
+    q.vR = static_cast<const double*>(b.vR)[p];
+    q.vZ = static_cast<const double*>(b.vZ)[p];
+    q.vT = static_cast<const double*>(b.vT)[p];
+    return q;
+}
+
+__device__ inline void set_dead(PlainState& q) { q.x1 = FP64_DEAD; }
+__device__ inline bool is_dead(const PlainState& q) { return q.x1 > 0.0; }
+
 __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams& sp, int s, int ns,
-                                     int64_t p, double* __restrict__ x1a, double* __restrict__ x2a,
-                                     double* __restrict__ vRa, double* __restrict__ vZa,
-                                     double* __restrict__ vTa, const double2* __restrict__ grad,
-                                     double* __restrict__ tally,
+                                     int64_t p, const PlainState& q, const PBuf& b,
+                                     const double2* __restrict__ grad, double* __restrict__ tally,
                                      unsigned long long* __restrict__ tally_count, int& i1n,
                                      int& i2n, double& f1n, double& f2n) {
-    const double x1 = x1a[p];
+    const double x1 = q.x1;
     if (x1 > 0.0) return -1;
+    double* __restrict__ x1a = static_cast<double*>(b.pos1);
+    double* __restrict__ x2a = static_cast<double*>(b.pos2);
+    double* __restrict__ vRa = static_cast<double*>(b.vR);
+    double* __restrict__ vZa = static_cast<double*>(b.vZ);
+    double* __restrict__ vTa = static_cast<double*>(b.vT);
     const int nx = gp.nx;
     const double alpha = gp.alpha;
-    const double x2 = x2a[p];
-    double vR = vRa[p], vZ = vZa[p], vT = vTa[p];
+    const double x2 = q.x2;
+    double vR = q.vR, vZ = q.vZ, vT = q.vT;
     int i1, i2;
     double f1, f2;
     locate64(gp, x1, x2, i1, i2, f1, f2);
@@ -385,16 +436,76 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
     return 0;
 }
 
-// ----------------------------------------------------------------- chunked push kernel
-// A workgroup pushes a chunk of PB * BLOCK consecutive (cell-sorted) particles,
-// then deposits their charge into an LDS window of nodes that covers the
-// chunk's new cells (or, when the chunk is spread too wide, a fixed window
-// around its mean cell; particles outside fall back to global atomics).  The
-// window's non-zero nodes are then added to the global deposit array once per
-// chunk.
-constexpr int PB = 8;
-constexpr int CHUNK = BLOCK * PB;
+// ----------------------------------------------------------------- ensemble push
+// One persistent launch pushes every (grain, species) task of the context.  The
+// tasks' particle slots are cut into chunks of PB * BLOCK consecutive
+// (tile-sorted) particles; k_plan_chunks lays the chunks of all tasks end to
+// end.  The chunk range is split into eight contiguous parts, one per XCD
+// (workgroup b runs on XCD b mod 8), so that the chunks of neighbouring tiles,
+// which read the same field nodes and add into the same deposit nodes, share
+// one L2.  A workgroup loads the whole state of its chunk into registers
+// first (all loads in flight together), derives the chunk's deposit window
+// from the loaded cells, then advances the particles and deposits their
+// charge into an LDS window of nodes; the window's non-zero nodes are added to
+// the global deposit array once per chunk.
+template <bool SPLIT> struct PushTraits;
+template <> struct PushTraits<true> {
+    using S = SplitState;
+    using T = float;
+    using A = unsigned long long;   // two 32-bit fixed-point sums per LDS word
+    static constexpr int PB = 8;    // particles per thread and chunk
+    static constexpr int AHEAD = 1; // look-ahead of the state loads (particles)
+};
+template <> struct PushTraits<false> {
+    using S = PlainState;
+    using T = double;
+    using A = double;
+    static constexpr int PB = 4;
+    static constexpr int AHEAD = 2;
+};
+
 constexpr int WIN_CAP = 4096;
+constexpr int WIN_MARGIN = 4;
+
+int push_chunk(bool split) { return BLOCK * (split ? PushTraits<true>::PB : PushTraits<false>::PB); }
+
+// chunks of every task, laid end to end: prefix[t] = first chunk of task t
+__global__ void __launch_bounds__(BLOCK)
+k_plan_chunks(const PushTask* __restrict__ tasks, int ntasks, int64_t chunk, int64_t* __restrict__ prefix) {
+    __shared__ int64_t cnt[BLOCK];
+    int64_t carry = 0;
+    for (int t0 = 0; t0 < ntasks; t0 += BLOCK) {
+        const int t = t0 + threadIdx.x;
+        int64_t c = 0;
+        if (t < ntasks) {
+            const PushTask& T = tasks[t];
+            c = (T.ctr->n[T.s] + chunk - 1) / chunk;
+        }
+        cnt[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < BLOCK && t0 + k < ntasks; ++k) {
+                prefix[t0 + k] = carry;
+                carry += cnt[k];
+            }
+            prefix[min(t0 + BLOCK, ntasks)] = carry;
+        }
+        __syncthreads();
+        carry = prefix[min(t0 + BLOCK, ntasks)];
+        __syncthreads();
+    }
+}
+
+// task of chunk c: the largest t with prefix[t] <= c
+__device__ inline int find_task(const int64_t* __restrict__ prefix, int ntasks, int64_t c) {
+    int lo = 0, hi = ntasks;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 __device__ inline void block_reduce7(int v[7], int (*red)[BLOCK / 64]) {
     // v: min i1, max i1, min i2, max i2, count, sum i1, sum i2
@@ -429,46 +540,27 @@ __device__ inline void block_reduce7(int v[7], int (*red)[BLOCK / 64]) {
 // widened by WIN_MARGIN cells on every side (clipped to the grid), or, if that
 // exceeds the LDS capacity, a 64-column window around the chunk's mean cell.
 // Particles whose new cell falls outside go straight to global atomics.
-constexpr int WIN_MARGIN = 4;
-
 struct Window {
     int wi0, wj0, W, H, C;   // first node, extent in nodes, lane-striped copies
     bool on;
 };
 
-template <bool SPLIT>
-__device__ inline void old_cell(const GrainParams& gp, const PBuf& b, int64_t p, int& i1, int& i2) {
-    if constexpr (SPLIT) {
-        const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
-        if (c < 0) { i1 = -1; return; }
-        i1 = cell_i1(c);
-        i2 = cell_i2(c);
-    } else {
-        const double x1 = static_cast<const double*>(b.pos1)[p];
-        if (x1 > 0.0) { i1 = -1; return; }
-        double f1, f2;
-        locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
-    }
+__device__ inline bool state_cell(const GrainParams&, const SplitState& q, int& i1, int& i2) {
+    if (q.c < 0) return false;
+    i1 = cell_i1(q.c);
+    i2 = cell_i2(q.c);
+    return true;
 }
 
-template <bool SPLIT>
-__device__ inline Window chunk_window(const GrainParams& gp, const PBuf& b, int64_t base, int64_t n,
-                                      int (*red)[BLOCK / 64]) {
-    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
-    for (int k = 0; k < PB; ++k) {
-        const int64_t p = base + k * BLOCK + threadIdx.x;
-        if (p >= n) break;
-        int i1, i2;
-        old_cell<SPLIT>(gp, b, p, i1, i2);
-        if (i1 < 0) continue;
-        v[0] = min(v[0], i1);
-        v[1] = max(v[1], i1);
-        v[2] = min(v[2], i2);
-        v[3] = max(v[3], i2);
-        v[4] += 1;
-        v[5] += i1;
-        v[6] += i2;
-    }
+__device__ inline bool state_cell(const GrainParams& gp, const PlainState& q, int& i1, int& i2) {
+    if (q.x1 > 0.0) return false;
+    double f1, f2;
+    locate64(gp, q.x1, q.x2, i1, i2, f1, f2);
+    return true;
+}
+
+// Window from the reduced bounding box v (see block_reduce7).
+__device__ inline Window window_from(const GrainParams& gp, int v[7], int (*red)[BLOCK / 64]) {
     block_reduce7(v, red);
     Window w;
     w.on = v[4] > 0;
@@ -493,11 +585,29 @@ __device__ inline Window chunk_window(const GrainParams& gp, const PBuf& b, int6
     return w;
 }
 
-template <typename T>
-__device__ inline void deposit_one(const GrainParams& gp, const Window& w, T* __restrict__ win,
-                                   T* __restrict__ dep, int i1, int i2, T f1, T f2) {  // FP64 form
-    const T a1 = T(1) - f1, a2 = T(1) - f2;
-    const T w00 = a1 * a2, w10 = f1 * a2, w01 = a1 * f2, w11 = f1 * f2;
+template <typename S, int PB>
+__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], int (*red)[BLOCK / 64]) {
+    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+        int i1, i2;
+        if (!state_cell(gp, st[k], i1, i2)) continue;
+        v[0] = min(v[0], i1);
+        v[1] = max(v[1], i1);
+        v[2] = min(v[2], i2);
+        v[3] = max(v[3], i2);
+        v[4] += 1;
+        v[5] += i1;
+        v[6] += i2;
+    }
+    return window_from(gp, v, red);
+}
+
+// FP64 form: one double per node copy.
+__device__ inline void deposit_one(const GrainParams& gp, const Window& w, double* __restrict__ win,
+                                   double* __restrict__ dep, int i1, int i2, double f1, double f2) {
+    const double a1 = 1.0 - f1, a2 = 1.0 - f2;
+    const double w00 = a1 * a2, w10 = f1 * a2, w01 = a1 * f2, w11 = f1 * f2;
     const int li = i1 - w.wi0, lj = i2 - w.wj0;
     if (li >= 0 && li < w.W - 1 && lj >= 0 && lj < w.H - 1) {
         const int C = w.C, cp = threadIdx.x & (C - 1);
@@ -516,18 +626,17 @@ __device__ inline void deposit_one(const GrainParams& gp, const Window& w, T* __
     }
 }
 
-template <typename T>
-__device__ inline void flush_window(const GrainParams& gp, const Window& w, T* __restrict__ win,
-                                    T* __restrict__ dep) {
+__device__ inline void flush_window(const GrainParams& gp, const Window& w, double* __restrict__ win,
+                                    double* __restrict__ dep) {
     const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
     for (int q = threadIdx.x; q < nodes_w; q += BLOCK) {
-        T val = T(0);
+        double val = 0.0;
         for (int c = 0; c < C; ++c) {
             const int a = q * C + ((c + q) & (C - 1));
             val += win[a];
-            win[a] = T(0);
+            win[a] = 0.0;
         }
-        if (val != T(0)) {
+        if (val != 0.0) {
             const int row = q / w.W;
             atomicAdd(&dep[(w.wj0 + row) * nx + w.wi0 + (q - row * w.W)], val);
         }
@@ -584,98 +693,280 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
     for (int q = threadIdx.x; q < nodes_w * C; q += BLOCK) win[q] = 0ull;
 }
 
-template <bool SPLIT>
-__global__ void __launch_bounds__(BLOCK)
-k_push(GrainParams gp, SpeciesParams sp, int s, int ns, PBuf b, const void* __restrict__ grad,
-       void* __restrict__ dep_v, DevCounters* __restrict__ ctr, double* __restrict__ tally,
-       unsigned long long* __restrict__ tally_count) {
-    using T = typename std::conditional<SPLIT, float, double>::type;
-    using A = typename std::conditional<SPLIT, unsigned long long, double>::type;
-    __shared__ A win[WIN_CAP];
-    __shared__ int red[7][BLOCK / 64];
-    T* dep = static_cast<T*>(dep_v);
-    const int64_t n = ctr->n[s];
-    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
-    __syncthreads();
-    SplitConsts K;
-    if constexpr (SPLIT) K = split_consts(gp, sp);
-    uint32_t n_live = 0, n_abs = 0, n_esc = 0;
-    for (int64_t chunk = blockIdx.x; chunk * CHUNK < n; chunk += gridDim.x) {
-        const int64_t base = chunk * CHUNK;
-        Window w;
-        w.on = false;
-        if (dep) w = chunk_window<SPLIT>(gp, b, base, n, red);
-#pragma unroll 1
-        for (int k = 0; k < PB; ++k) {
-            const int64_t p = base + k * BLOCK + threadIdx.x;
-            if (p >= n) break;
-            int a, c;
-            T f, g;
-            int st;
-            if constexpr (SPLIT)
-                st = push_split_one(gp, sp, K, s, ns, p, static_cast<int32_t*>(b.pos0),
-                                    static_cast<float*>(b.pos1), static_cast<float*>(b.pos2),
-                                    static_cast<float*>(b.vR), static_cast<float*>(b.vZ),
-                                    static_cast<float*>(b.vT), static_cast<const float2*>(grad),
-                                    tally, tally_count, a, c, f, g);
-            else
-                st = push_plain_one(gp, sp, s, ns, p, static_cast<double*>(b.pos1),
-                                    static_cast<double*>(b.pos2), static_cast<double*>(b.vR),
-                                    static_cast<double*>(b.vZ), static_cast<double*>(b.vT),
-                                    static_cast<const double2*>(grad), tally, tally_count, a, c, f,
-                                    g);
-            if (st < 0) continue;
-            ++n_live;
-            if (st == 1) { ++n_abs; continue; }
-            if (st == 2) { ++n_esc; continue; }
-            if (w.on) deposit_one(gp, w, win, dep, a, c, f, g);
-        }
-        if (w.on) {
-            __syncthreads();
-            flush_window(gp, w, win, dep);
-            __syncthreads();
-        }
-    }
+__device__ inline SplitState load_state(const PBuf& b, int64_t p, SplitState*) { return load_split(b, p); }
+__device__ inline PlainState load_state(const PBuf& b, int64_t p, PlainState*) { return load_plain(b, p); }
+
+// chunk range of this workgroup's XCD: [lo, hi), stride = workgroups per XCD
+__device__ inline void xcd_range(int64_t total, int64_t& first, int64_t& hi, int& stride) {
+    const int xcd = blockIdx.x & 7;
+    stride = gridDim.x >> 3;
+    const int64_t lo = total * xcd / 8;
+    hi = total * (xcd + 1) / 8;
+    first = lo + (blockIdx.x >> 3);
+}
+
+// Parameters of the task a workgroup is working on, reloaded only when its
+// chunk index crosses into the next task (the chunk index only grows), so the
+// chain prefix -> task -> counters -> buffers is paid once per task, not per
+// chunk.
+template <typename T>
+struct TaskView {
+    GrainParams gp;
+    SpeciesParams sp;
+    PBuf b;
+    const void* grad;
+    T* dep;
+    DevCounters* ctr;
+    double* tally;
+    unsigned long long* tally_count;
+    int64_t n, first_chunk, end_chunk;
+    int s, ns;
+};
+
+template <typename T>
+__device__ inline void load_task(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix,
+                                 int ntasks, int64_t c, bool deposit, TaskView<T>& v) {
+    const int t = find_task(prefix, ntasks, c);
+    const PushTask& task = tasks[t];
+    v.first_chunk = prefix[t];
+    v.end_chunk = prefix[t + 1];
+    v.gp = task.gp;
+    v.sp = task.sp;
+    v.ctr = task.ctr;
+    v.s = task.s;
+    v.ns = task.ns;
+    v.grad = task.grad;
+    v.dep = deposit ? static_cast<T*>(task.dep) : nullptr;
+    v.tally = task.tally;
+    v.tally_count = task.tally_count;
+    v.n = v.ctr->n[v.s];
+    v.b = task.buf[v.ctr->cur[v.s]];
+}
+
+__device__ inline void flush_counts(DevCounters* ctr, int s, uint32_t& n_live, uint32_t& n_abs, uint32_t& n_esc) {
     block_count_add(n_live, reinterpret_cast<unsigned long long*>(&ctr->pushed[s]));
     block_count_add(n_abs, reinterpret_cast<unsigned long long*>(&ctr->absorbed[s]));
     block_count_add(n_esc, reinterpret_cast<unsigned long long*>(&ctr->escaped[s]));
+    n_live = n_abs = n_esc = 0;
+}
+
+// Loading a chunk: the keys (packed cell / FP64 position) of all its particles
+// first -- the deposit window needs them before anything else -- then the rest
+// of each particle's state one particle (plus AHEAD look-ahead) at a time
+// inside a rolled loop, which keeps the loads in flight per wave close to what
+// the HBM pipe needs without inflating the register count.
+
+struct SplitKey { int32_t c; };
+struct PlainKey { double x1, x2; };
+
+__device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, SplitKey& k) {
+    k.c = p < n ? static_cast<const int32_t*>(b.pos0)[p] : DEAD;
+}
+__device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, PlainKey& k) {
+    if (p < n) {
+        k.x1 = static_cast<const double*>(b.pos1)[p];
+        k.x2 = static_cast<const double*>(b.pos2)[p];
+    } else {
+        k.x1 = FP64_DEAD;
+        k.x2 = 0.0;
+    }
+}
+
+__device__ inline bool key_cell(const GrainParams&, const SplitKey& k, int& i1, int& i2) {
+    if (k.c < 0) return false;
+    i1 = cell_i1(k.c);
+    i2 = cell_i2(k.c);
+    return true;
+}
+__device__ inline bool key_cell(const GrainParams& gp, const PlainKey& k, int& i1, int& i2) {
+    if (k.x1 > 0.0) return false;
+    double f1, f2;
+    locate64(gp, k.x1, k.x2, i1, i2, f1, f2);
+    return true;
+}
+
+__device__ inline void load_rest(const PBuf& b, int64_t p, const SplitKey& k, SplitState& q) {
+    q.c = k.c;
+    if (k.c < 0) return;
+    q.f1 = static_cast<const float*>(b.pos1)[p];
+    q.f2 = static_cast<const float*>(b.pos2)[p];
+    q.vR = static_cast<const float*>(b.vR)[p];
+    q.vZ = static_cast<const float*>(b.vZ)[p];
+    q.vT = static_cast<const float*>(b.vT)[p];
+}
+__device__ inline void load_rest(const PBuf& b, int64_t p, const PlainKey& k, PlainState& q) {
+    q.x1 = k.x1;
+    q.x2 = k.x2;
+    if (k.x1 > 0.0) return;
+    q.vR = static_cast<const double*>(b.vR)[p];
+    q.vZ = static_cast<const double*>(b.vZ)[p];
+    q.vT = static_cast<const double*>(b.vT)[p];
+}
+
+template <typename K, int PB>
+__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], int (*red)[BLOCK / 64]) {
+    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+        int i1, i2;
+        if (!key_cell(gp, key[k], i1, i2)) continue;
+        v[0] = min(v[0], i1);
+        v[1] = max(v[1], i1);
+        v[2] = min(v[2], i2);
+        v[3] = max(v[3], i2);
+        v[4] += 1;
+        v[5] += i1;
+        v[6] += i2;
+    }
+    return window_from(gp, v, red);
+}
+
+template <bool SPLIT> struct KeyOf;
+template <> struct KeyOf<true> { using K = SplitKey; };
+template <> struct KeyOf<false> { using K = PlainKey; };
+
+template <bool SPLIT>
+__device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix,
+                                            int ntasks, int deposit) {
+    using Tr = PushTraits<SPLIT>;
+    constexpr int PUSH_AHEAD = Tr::AHEAD;
+    using S = typename Tr::S;
+    using T = typename Tr::T;
+    using A = typename Tr::A;
+    using Key = typename KeyOf<SPLIT>::K;
+    constexpr int PB = Tr::PB;
+    constexpr int CHUNK = PB * BLOCK;
+    __shared__ A win[WIN_CAP];
+    __shared__ int red[7][BLOCK / 64];
+    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
+    __syncthreads();
+    int64_t c, hi;
+    int stride;
+    xcd_range(prefix[ntasks], c, hi, stride);
+    TaskView<T> v;
+    v.end_chunk = -1;
+    v.ctr = nullptr;
+    SplitConsts K;
+    uint32_t n_live = 0, n_abs = 0, n_esc = 0;
+    for (; c < hi; c += stride) {
+        if (c >= v.end_chunk) {
+            if (v.ctr) flush_counts(v.ctr, v.s, n_live, n_abs, n_esc);
+            load_task(tasks, prefix, ntasks, c, deposit != 0, v);
+            if constexpr (SPLIT) K = split_consts(v.gp, v.sp);
+        }
+        const int64_t base = (c - v.first_chunk) * CHUNK + threadIdx.x;
+        Key key[PB + PUSH_AHEAD];
+#pragma unroll
+        for (int k = 0; k < PB; ++k) load_key(v.b, base + k * BLOCK, v.n, key[k]);
+#pragma unroll
+        for (int k = PB; k < PB + PUSH_AHEAD; ++k) load_key(v.b, 0, 0, key[k]);
+        Window w;
+        w.on = false;
+        if (v.dep) w = keys_window(v.gp, reinterpret_cast<const Key(&)[PB]>(key), red);
+        S ahead[PUSH_AHEAD + 1];
+#pragma unroll
+        for (int a = 0; a < PUSH_AHEAD; ++a) load_rest(v.b, base + a * BLOCK, key[a], ahead[a]);
+#pragma unroll 1
+        for (int k = 0; k < PB; ++k) {
+            const int64_t p = base + k * BLOCK;
+            // the state PUSH_AHEAD particles ahead starts loading before this one is advanced
+            load_rest(v.b, p + PUSH_AHEAD * BLOCK, key[PUSH_AHEAD], ahead[PUSH_AHEAD]);
+            const S cur = ahead[0];
+#pragma unroll
+            for (int a = 0; a < PUSH_AHEAD; ++a) ahead[a] = ahead[a + 1];
+#pragma unroll
+            for (int a = 0; a < PB + PUSH_AHEAD - 1; ++a) key[a] = key[a + 1];
+            int ia, ic;
+            T f, g;
+            int r;
+            if constexpr (SPLIT)
+                r = push_split_one(v.gp, v.sp, K, v.s, v.ns, p, cur, v.b,
+                                   static_cast<const float2*>(v.grad), v.tally, v.tally_count, ia, ic, f, g);
+            else
+                r = push_plain_one(v.gp, v.sp, v.s, v.ns, p, cur, v.b,
+                                   static_cast<const double2*>(v.grad), v.tally, v.tally_count, ia, ic, f, g);
+            if (r < 0) continue;
+            ++n_live;
+            if (r == 1) { ++n_abs; continue; }
+            if (r == 2) { ++n_esc; continue; }
+            if (w.on) deposit_one(v.gp, w, win, v.dep, ia, ic, f, g);
+        }
+        if (w.on) {
+            __syncthreads();
+            flush_window(v.gp, w, win, v.dep);
+            __syncthreads();
+        }
+    }
+    if (v.ctr) flush_counts(v.ctr, v.s, n_live, n_abs, n_esc);
+}
+
+// FP32: capped at 128 registers so four waves per SIMD stay resident (the
+// kernel is bound by memory latency); FP64 keeps its registers.
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_push_split(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
+    push_chunks<true>(tasks, prefix, ntasks, deposit);
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_push_plain(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
+    push_chunks<false>(tasks, prefix, ntasks, deposit);
 }
 
 // ----------------------------------------------------------------- deposit only
-// Deposit of the current particles (initial field, standalone solves) with the
-// same chunk windows as the push.
+// Deposit of the current particles of every task (initial field, standalone
+// solves) with the same chunks and windows as the push.
+__device__ inline void state_offsets(const GrainParams&, const SplitState& q, int& i1, int& i2, float& f1, float& f2) {
+    i1 = cell_i1(q.c);
+    i2 = cell_i2(q.c);
+    f1 = q.f1;
+    f2 = q.f2;
+}
+
+__device__ inline void state_offsets(const GrainParams& gp, const PlainState& q, int& i1, int& i2, double& f1,
+                                     double& f2) {
+    locate64(gp, q.x1, q.x2, i1, i2, f1, f2);
+}
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_deposit(GrainParams gp, int s, PBuf b, void* __restrict__ dep_v, const DevCounters* __restrict__ ctr) {
-    using T = typename std::conditional<SPLIT, float, double>::type;
-    using A = typename std::conditional<SPLIT, unsigned long long, double>::type;
+k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks) {
+    using Tr = PushTraits<SPLIT>;
+    using S = typename Tr::S;
+    using T = typename Tr::T;
+    using A = typename Tr::A;
+    constexpr int PB = Tr::PB;
+    constexpr int CHUNK = PB * BLOCK;
     __shared__ A win[WIN_CAP];
     __shared__ int red[7][BLOCK / 64];
-    T* dep = static_cast<T*>(dep_v);
-    const int64_t n = ctr->n[s];
     for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
     __syncthreads();
-    for (int64_t chunk = blockIdx.x; chunk * CHUNK < n; chunk += gridDim.x) {
-        const int64_t base = chunk * CHUNK;
-        const Window w = chunk_window<SPLIT>(gp, b, base, n, red);
-        if (!w.on) continue;
+    int64_t c, hi;
+    int stride;
+    xcd_range(prefix[ntasks], c, hi, stride);
+    for (; c < hi; c += stride) {
+        const int t = find_task(prefix, ntasks, c);
+        const PushTask& task = tasks[t];
+        const GrainParams gp = task.gp;
+        const int s = task.s;
+        const int64_t n = task.ctr->n[s];
+        const PBuf b = task.buf[task.ctr->cur[s]];
+        T* dep = static_cast<T*>(task.dep);
+        const int64_t base = (c - prefix[t]) * CHUNK;
+        S st[PB];
+#pragma unroll
         for (int k = 0; k < PB; ++k) {
             const int64_t p = base + k * BLOCK + threadIdx.x;
-            if (p >= n) break;
+            if (p < n) st[k] = load_state(b, p, (S*)nullptr);
+            else set_dead(st[k]);
+        }
+        const Window w = chunk_window(gp, st, red);
+        if (!w.on) continue;
+#pragma unroll
+        for (int k = 0; k < PB; ++k) {
+            if (is_dead(st[k])) continue;
             int i1, i2;
             T f1, f2;
-            if constexpr (SPLIT) {
-                const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
-                if (c < 0) continue;
-                i1 = cell_i1(c);
-                i2 = cell_i2(c);
-                f1 = static_cast<const float*>(b.pos1)[p];
-                f2 = static_cast<const float*>(b.pos2)[p];
-            } else {
-                const double x1 = static_cast<const double*>(b.pos1)[p];
-                if (x1 > 0.0) continue;
-                locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
-            }
+            state_offsets(gp, st[k], i1, i2, f1, f2);
             deposit_one(gp, w, win, dep, i1, i2, f1, f2);
         }
         __syncthreads();
@@ -770,25 +1061,61 @@ k_set(GrainParams gp, int64_t n, bool split, PBuf b, const double* __restrict__ 
 }
 
 // ----------------------------------------------------------------- injection
+// Per task: the step's count from the 2^-32 fixed-point accumulator (exact
+// integers), the slots it takes (capacity permitting; the excess sets the
+// sticky overflow flag), its first id and the Philox stream (= the grain's
+// step index).
+__global__ void __launch_bounds__(BLOCK)
+k_inject_plan(const PushTask* __restrict__ tasks, int ntasks) {
+    for (int t = threadIdx.x; t < ntasks; t += BLOCK) {
+        const PushTask& T = tasks[t];
+        DevCounters* ctr = T.ctr;
+        const int s = T.s;
+        const uint64_t acc = ctr->inj_acc[s] + T.inj_inc;
+        const int64_t n_new = (int64_t)(acc >> 32);
+        ctr->inj_acc[s] = acc & 0xFFFFFFFFull;
+        const int64_t n = ctr->n[s];
+        const int64_t room = T.capacity > n ? T.capacity - n : 0;
+        const int64_t placed = n_new < room ? n_new : room;
+        if (placed < n_new) ctr->overflow = 1u;
+        ctr->inj_base[s] = n;
+        ctr->inj_new[s] = n_new;
+        ctr->inj_id0[s] = ctr->next_id[s];
+        ctr->n[s] = n + placed;
+        ctr->injected[s] += (uint64_t)placed;
+        ctr->next_id[s] += (uint32_t)n_new;
+        if (s == 0) {
+            ctr->inj_tag = (uint32_t)(ctr->step & 0xFFFFFFFFull);
+            ctr->step += 1;
+        }
+    }
+}
+
 // Flux-Maxwellian injection at x1_out: x2 with density proportional to eq. (4),
 // inward normal speed Rayleigh(sigma), tangential normal(0, sigma^2), then a
 // straight partial step U * dt with the usual boundary tests; the survivors
-// deposit their charge.  Slot = n_slots + k, id = next_id + k.
+// deposit their charge.  Slot = base + k, id = id0 + k; blockIdx.y = task.
 __global__ void __launch_bounds__(BLOCK)
-k_inject(GrainParams gp, SpeciesParams sp, int s, int ns, int64_t n_new, uint32_t stream_tag,
-         int64_t capacity, bool split, PBuf b, void* dep, DevCounters* ctr, double* tally,
-         unsigned long long* tally_count) {
-    const int64_t base = ctr->n[s];
-    const uint32_t id0 = ctr->next_id[s];
+k_inject(const PushTask* __restrict__ tasks, bool split, int deposit) {
+    const PushTask& T = tasks[blockIdx.y];
+    const GrainParams gp = T.gp;
+    const SpeciesParams sp = T.sp;
+    DevCounters* ctr = T.ctr;
+    const int s = T.s, ns = T.ns;
+    const int64_t n_new = ctr->inj_new[s];
+    const int64_t base = ctr->inj_base[s];
+    const uint32_t id0 = ctr->inj_id0[s];
+    const uint32_t stream_tag = ctr->inj_tag;
+    const PBuf b = T.buf[ctr->cur[s]];
+    void* dep = deposit ? T.dep : nullptr;
+    double* tally = T.tally;
+    unsigned long long* tally_count = T.tally_count;
     const double alpha = gp.alpha, xo = gp.x1_out;
     uint32_t n_abs = 0, n_esc = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_new;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t slot = base + k;
-        if (slot >= capacity) {
-            atomicOr(&ctr->overflow, 1u);
-            continue;
-        }
+        if (slot >= T.capacity) continue;
         double x2 = 0;
         for (int a = 0; a < MAX_ATTEMPTS; ++a) {
             const U4 u = philox4x32_10(U4{stream_tag, (uint32_t)s | (P_INJ_POS << 8), (uint32_t)k,
@@ -847,14 +1174,6 @@ k_inject(GrainParams gp, SpeciesParams sp, int s, int ns, int64_t n_new, uint32_
     block_count_add(n_esc, reinterpret_cast<unsigned long long*>(&ctr->escaped[s]));
 }
 
-__global__ void k_add_slots(DevCounters* ctr, int s, int64_t n_new, int64_t capacity) {
-    const int64_t n = ctr->n[s];
-    const int64_t placed = (n + n_new > capacity) ? (capacity > n ? capacity - n : 0) : n_new;
-    ctr->n[s] = n + placed;
-    ctr->injected[s] += (uint64_t)placed;
-    ctr->next_id[s] += (uint32_t)n_new;
-}
-
 // ----------------------------------------------------------------- readback
 __global__ void __launch_bounds__(BLOCK)
 k_readback(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
@@ -896,11 +1215,16 @@ k_readback(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restr
 // row-major order, x1 fastest); inside a tile the order is arbitrary.  That is
 // all the push needs: a chunk of consecutive particles then covers one tile (or
 // a few), so its deposit window and its field nodes stay small.  The sort is a
-// one-pass counting sort without global atomics: each of SORT_BLOCKS blocks
-// takes a contiguous slot range, builds the histogram of its tiles in LDS,
-// the histograms are scanned tile-major, and each block scatters its
-// particles to its own offsets.  Dead slots are dropped on the way.
-constexpr int SORT_BLOCKS = 1024;
+// one-pass counting sort without global atomics, run for every task at once
+// (blockIdx.y = task): each of the task's sort_blocks workgroups takes a
+// contiguous slot range and builds the histogram of its tiles in LDS, the
+// histograms are scanned tile-major, and each workgroup scatters its particles
+// to its own offsets.  Dead slots are dropped on the way.
+constexpr int SORT_BLOCKS_MAX = 1024;
+constexpr int SCAN_SEG = 4096;      // histogram entries per scan workgroup
+
+int max_sort_blocks() { return SORT_BLOCKS_MAX; }
+int scan_seg_len() { return SCAN_SEG; }
 
 __device__ inline int tile_key(const GrainParams& gp, bool split, const PBuf& b, int64_t p) {
     int i1, i2;
@@ -931,22 +1255,25 @@ __device__ inline void wave_runs(int key, int& head_lane, int& run_len, bool& is
     run_len = (gt ? (__ffsll((long long)gt) - 1) : 64) - lane;
 }
 
-__device__ inline void sort_range(const DevCounters* ctr, int s, int64_t& lo, int64_t& hi) {
-    const int64_t n = ctr->n[s];
-    const int64_t per = (n + SORT_BLOCKS - 1) / SORT_BLOCKS;
+__device__ inline void sort_range(int64_t n, int blocks, int64_t& lo, int64_t& hi) {
+    const int64_t per = (n + blocks - 1) / blocks;
     lo = min<int64_t>((int64_t)blockIdx.x * per, n);
     hi = min<int64_t>(lo + per, n);
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_tile_hist(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
-            int* __restrict__ hist) {
+k_tile_hist(const PushTask* __restrict__ tasks, bool split) {
     extern __shared__ int lh[];
+    const PushTask& T = tasks[blockIdx.y];
+    const int SB = T.sort_blocks;
+    if ((int)blockIdx.x >= SB) return;
+    const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
     for (int t = threadIdx.x; t < nt; t += BLOCK) lh[t] = 0;
     __syncthreads();
+    const PBuf b = T.buf[T.ctr->cur[T.s]];
     int64_t lo, hi;
-    sort_range(ctr, s, lo, hi);
+    sort_range(T.ctr->n[T.s], SB, lo, hi);
     for (int64_t base = lo; base < hi; base += BLOCK) {
         const int64_t p = base + threadIdx.x;
         const int key = p < hi ? tile_key(gp, split, b, p) : -1;
@@ -956,19 +1283,110 @@ k_tile_hist(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __rest
         if (is_head && key >= 0) atomicAdd(&lh[key], len);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nt; t += BLOCK) hist[(size_t)t * SORT_BLOCKS + blockIdx.x] = lh[t];
+    for (int t = threadIdx.x; t < nt; t += BLOCK) T.hist[(size_t)t * SB + blockIdx.x] = lh[t];
+}
+
+// Exclusive scan of every task's histogram (length ntiles * sort_blocks) in
+// three passes: segment sums, scan of the segment sums (which also gives the
+// live count), scan inside the segments.
+__device__ inline int block_scan_excl(int v, int* tmp, int& total) {
+    // exclusive scan of one int per thread over the block
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) tmp[w] = x;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+        if (k < w) off += tmp[k];
+        total += tmp[k];
+    }
+    __syncthreads();
+    return off + x - v;
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_tile_scatter(GrainParams gp, int s, bool split, PBuf src, PBuf dst,
-               const DevCounters* __restrict__ ctr, const int* __restrict__ offset) {
+k_scan_reduce(const PushTask* __restrict__ tasks) {
+    const PushTask& T = tasks[blockIdx.y];
+    const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
+    const int64_t lo = (int64_t)blockIdx.x * SCAN_SEG;
+    if (lo >= len) return;
+    const int64_t hi = min<int64_t>(lo + SCAN_SEG, len);
+    int v = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) v += T.hist[i];
+    __shared__ int tmp[BLOCK / 64];
+    int total;
+    (void)block_scan_excl(v, tmp, total);
+    if (threadIdx.x == 0) T.seg[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_segs(const PushTask* __restrict__ tasks) {
+    const PushTask& T = tasks[blockIdx.x];
+    const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
+    const int nseg = (int)((len + SCAN_SEG - 1) / SCAN_SEG);
+    __shared__ int tmp[1024 / 64];
+    int carry = 0;
+    for (int k0 = 0; k0 < nseg; k0 += 1024) {
+        const int k = k0 + threadIdx.x;
+        const int v = k < nseg ? T.seg[k] : 0;
+        int total;
+        const int ex = block_scan_excl(v, tmp, total);
+        if (k < nseg) T.seg[k] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        T.hist_off[len] = carry;
+        T.ctr->n_sorted[T.s] = carry;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_scan_apply(const PushTask* __restrict__ tasks) {
+    const PushTask& T = tasks[blockIdx.y];
+    const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
+    const int64_t lo = (int64_t)blockIdx.x * SCAN_SEG;
+    if (lo >= len) return;
+    constexpr int PER = SCAN_SEG / BLOCK;
+    const int64_t i0 = lo + (int64_t)threadIdx.x * PER;
+    int v[PER];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = (i0 + k < len) ? T.hist[i0 + k] : 0;
+        sum += v[k];
+    }
+    __shared__ int tmp[BLOCK / 64];
+    int total;
+    int run = T.seg[blockIdx.x] + block_scan_excl(sum, tmp, total);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (i0 + k < len) T.hist_off[i0 + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
     extern __shared__ int cur[];
+    const PushTask& T = tasks[blockIdx.y];
+    const int SB = T.sort_blocks;
+    if ((int)blockIdx.x >= SB) return;
+    const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
-    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = offset[(size_t)t * SORT_BLOCKS + blockIdx.x];
+    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = T.hist_off[(size_t)t * SB + blockIdx.x];
     __syncthreads();
+    const int which = T.ctr->cur[T.s];
+    const PBuf src = T.buf[which];
+    const PBuf dst = T.buf[1 - which];
     const int lane = threadIdx.x & 63;
     int64_t lo, hi;
-    sort_range(ctr, s, lo, hi);
+    sort_range(T.ctr->n[T.s], SB, lo, hi);
     for (int64_t base = lo; base < hi; base += BLOCK) {
         const int64_t p = base + threadIdx.x;
         const int key = p < hi ? tile_key(gp, split, src, p) : -1;
@@ -997,11 +1415,29 @@ k_tile_scatter(GrainParams gp, int s, bool split, PBuf src, PBuf dst,
     }
 }
 
-__global__ void k_sort_live(DevCounters* ctr, int s, const int* offset, int total_index) {
-    ctr->n_sorted[s] = offset[total_index];
+// the sorted buffer becomes the current one; slots = live particles
+__global__ void __launch_bounds__(BLOCK)
+k_sort_commit(const PushTask* __restrict__ tasks, int ntasks) {
+    for (int t = threadIdx.x; t < ntasks; t += BLOCK) {
+        DevCounters* ctr = tasks[t].ctr;
+        const int s = tasks[t].s;
+        ctr->n[s] = ctr->n_sorted[s];
+        ctr->cur[s] = 1 - ctr->cur[s];
+    }
 }
 
-__global__ void k_sort_commit(DevCounters* ctr, int s) { ctr->n[s] = ctr->n_sorted[s]; }
+__global__ void __launch_bounds__(BLOCK)
+k_count_live(int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
+             unsigned long long* out) {
+    const int64_t n = ctr->n[s];
+    uint32_t live = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (split) live += static_cast<const int32_t*>(b.pos0)[p] >= 0;
+        else live += !(static_cast<const double*>(b.pos1)[p] > 0.0);
+    }
+    block_count_add(live, out);
+}
 
 // ----------------------------------------------------------------- launchers
 static int grid_for(apic_ctx* ctx, int64_t n) {
@@ -1012,49 +1448,75 @@ static int grid_for(apic_ctx* ctx, int64_t n) {
 
 static bool is_split(apic_ctx* ctx) { return ctx->opts.precision == APIC_FP32_SPLIT; }
 
-hipError_t launch_push(apic_ctx* ctx, Grain& g, int s) {
-    const PBuf& b = g.buf[s][g.cur[s]];
-    const int64_t chunks = (g.host_slots[s] + CHUNK - 1) / CHUNK;
-    const int64_t cap = (int64_t)ctx->num_cus * 8;
-    const int grid = (int)std::max<int64_t>(1, std::min(chunks, cap));
-    void* dep = ctx->opts.frozen_field ? nullptr : g.dep[s];
-    if (is_split(ctx))
-        hipLaunchKernelGGL(k_push<true>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
-                           g.ns, b, g.grad, dep, g.ctr, g.tally, g.tally_count);
+// Workgroups of a persistent launch: push_wg_per_cu per compute unit, at most
+// what stays resident at once (a second round of workgroups would run alone
+// after the first and leave the chip underfilled), a multiple of 8 (XCDs).
+template <typename K>
+static int persistent_grid(apic_ctx* ctx, K kernel) {
+    int resident = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, BLOCK, 0) != hipSuccess || resident < 1)
+        resident = 1;
+    const int per_cu = std::min(ctx->sched.push_wg_per_cu, resident);
+    int g = ctx->num_cus * per_cu;
+    g = g / 8 * 8;
+    return g < 8 ? 8 : g;
+}
+
+int push_resident_per_cu(apic_ctx* ctx) {
+    int resident = 0;
+    if (ctx->opts.precision == APIC_FP32_SPLIT)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_split, BLOCK, 0);
     else
-        hipLaunchKernelGGL(k_push<false>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, g.sp[s], s,
-                           g.ns, b, g.grad, dep, g.ctr, g.tally, g.tally_count);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_plain, BLOCK, 0);
+    return resident < 1 ? 1 : resident;
+}
+
+hipError_t launch_push(apic_ctx* ctx, bool deposit) {
+    const bool split = is_split(ctx);
+    hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
+                       (int64_t)push_chunk(split), ctx->chunk_prefix);
+    if (split)
+        hipLaunchKernelGGL(k_push_split, dim3(persistent_grid(ctx, k_push_split)), dim3(BLOCK), 0, ctx->stream,
+                           ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_push_plain, dim3(persistent_grid(ctx, k_push_plain)), dim3(BLOCK), 0, ctx->stream,
+                           ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_deposit_all(apic_ctx* ctx, Grain& g, int s) {
-    const PBuf& b = g.buf[s][g.cur[s]];
-    const int64_t chunks = (g.host_slots[s] + CHUNK - 1) / CHUNK;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)ctx->num_cus * 8));
-    if (is_split(ctx))
-        hipLaunchKernelGGL(k_deposit<true>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s, b,
-                           g.dep[s], g.ctr);
+hipError_t launch_deposit(apic_ctx* ctx) {
+    const bool split = is_split(ctx);
+    hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
+                       (int64_t)push_chunk(split), ctx->chunk_prefix);
+    if (split)
+        hipLaunchKernelGGL(k_deposit<true>, dim3(persistent_grid(ctx, k_deposit<true>)), dim3(BLOCK), 0,
+                           ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     else
-        hipLaunchKernelGGL(k_deposit<false>, dim3(grid), dim3(BLOCK), 0, ctx->stream, g.gp, s, b,
-                           g.dep[s], g.ctr);
+        hipLaunchKernelGGL(k_deposit<false>, dim3(persistent_grid(ctx, k_deposit<false>)), dim3(BLOCK), 0,
+                           ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     return hipGetLastError();
 }
 
-hipError_t launch_inject(apic_ctx* ctx, Grain& g, int s, int64_t n_new, uint32_t stream_tag) {
-    const PBuf& b = g.buf[s][g.cur[s]];
-    void* dep = ctx->opts.frozen_field ? nullptr : g.dep[s];
-    hipLaunchKernelGGL(k_inject, dim3(grid_for(ctx, n_new)), dim3(BLOCK), 0, ctx->stream, g.gp,
-                       g.sp[s], s, g.ns, n_new, stream_tag, g.capacity[s], is_split(ctx), b, dep,
-                       g.ctr, g.tally, g.tally_count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_add_slots(ctx, g, s, n_new);
+hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
+    hipLaunchKernelGGL(k_inject_plan, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks);
+    const int64_t want = (ctx->max_inj_bound + BLOCK - 1) / BLOCK;
+    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024));
+    hipLaunchKernelGGL(k_inject, dim3(bx, ctx->ntasks), dim3(BLOCK), 0, ctx->stream, ctx->tasks,
+                       is_split(ctx), deposit ? 1 : 0);
+    return hipGetLastError();
 }
 
-hipError_t launch_add_slots(apic_ctx* ctx, Grain& g, int s, int64_t n_new) {
-    hipLaunchKernelGGL(k_add_slots, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s, n_new,
-                       g.capacity[s]);
-    g.host_slots[s] = std::min<int64_t>(g.host_slots[s] + n_new, g.capacity[s]);
+hipError_t launch_sort(apic_ctx* ctx) {
+    const bool split = is_split(ctx);
+    const size_t lds = sizeof(int) * (size_t)ctx->max_ntiles;
+    const dim3 sgrid(ctx->max_sort_blocks, ctx->ntasks);
+    const dim3 cgrid(ctx->max_segs, ctx->ntasks);
+    hipLaunchKernelGGL(k_tile_hist, sgrid, dim3(BLOCK), lds, ctx->stream, ctx->tasks, split);
+    hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, ctx->tasks);
+    hipLaunchKernelGGL(k_scan_segs, dim3(ctx->ntasks), dim3(1024), 0, ctx->stream, ctx->tasks);
+    hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, ctx->tasks);
+    hipLaunchKernelGGL(k_tile_scatter, sgrid, dim3(BLOCK), lds, ctx->stream, ctx->tasks, split);
+    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks);
     return hipGetLastError();
 }
 
@@ -1085,57 +1547,10 @@ hipError_t launch_readback(apic_ctx* ctx, Grain& g, int s, int64_t n, double* dx
     return hipGetLastError();
 }
 
-hipError_t launch_sort(apic_ctx* ctx, Grain& g, int s) {
-    const PBuf& src = g.buf[s][g.cur[s]];
-    const PBuf& dst = g.buf[s][1 - g.cur[s]];
-    const size_t lds = sizeof(int) * (size_t)g.gp.ntiles;
-    const int total = g.gp.ntiles * SORT_BLOCKS;
-    hipLaunchKernelGGL(k_tile_hist, dim3(SORT_BLOCKS), dim3(BLOCK), lds, ctx->stream, g.gp, s,
-                       is_split(ctx), src, g.ctr, g.sort_count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    size_t bytes = g.scan_tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(g.scan_tmp, bytes, g.sort_count, g.sort_offset, total + 1,
-                                         ctx->stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_live, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s, g.sort_offset, total);
-    hipLaunchKernelGGL(k_tile_scatter, dim3(SORT_BLOCKS), dim3(BLOCK), lds, ctx->stream, g.gp, s,
-                       is_split(ctx), src, dst, g.ctr, g.sort_offset);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(1), 0, ctx->stream, g.ctr, s);
-    g.cur[s] = 1 - g.cur[s];
-    return hipGetLastError();
-}
-
-int sort_blocks() { return SORT_BLOCKS; }
-
-size_t scan_temp_bytes(int n) {
-    size_t bytes = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (int*)nullptr, (int*)nullptr, n);
-    return bytes;
-}
-
-}  // namespace apic
-
-namespace apic {
-
-__global__ void __launch_bounds__(BLOCK)
-k_count_live(int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
-             unsigned long long* out) {
-    const int64_t n = ctr->n[s];
-    uint32_t live = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        if (split) live += static_cast<const int32_t*>(b.pos0)[p] >= 0;
-        else live += !(static_cast<const double*>(b.pos1)[p] > 0.0);
-    }
-    block_count_add(live, out);
-}
-
 hipError_t launch_count_live(apic_ctx* ctx, Grain& g, int s, unsigned long long* out) {
     hipError_t e = launch_fill(ctx, out, sizeof(unsigned long long));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_count_live, dim3(grid_for(ctx, g.host_slots[s])), dim3(BLOCK), 0,
+    hipLaunchKernelGGL(k_count_live, dim3(grid_for(ctx, g.capacity[s])), dim3(BLOCK), 0,
                        ctx->stream, s, is_split(ctx), g.buf[s][g.cur[s]], g.ctr, out);
     return hipGetLastError();
 }

@@ -1,0 +1,181 @@
+"""GPU runs of an ensemble of grains in one context (one launch sequence over
+all grains), through the C ABI, against the oracle and against one-grain
+contexts: different shapes, fields, grids (one small enough to be solved by the
+dense inverse on its finest level), particle counts and species parameters."""
+import numpy as np
+import pytest
+
+import paper_2307_11107_amd as apic
+from gpu_util import particle_error
+from oracle.pic import Config, Simulation, Species
+from oracle.poisson import source_from_density
+from synthetic_inputs import random_particles, smooth_density
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = apic.APIC_FP64, apic.APIC_FP32_SPLIT
+SEED = 5
+
+ENSEMBLE = [
+    dict(alpha=0.0, wce=0.0, n1=32, n2=32, x1_out=-0.1, kappa=2.0, mi=100.0, Ti=1.0, n_macro=20_000),
+    dict(alpha=0.15, wce=0.5, n1=48, n2=32, x1_out=-0.1, kappa=1.0, mi=400.0, Ti=0.5, n_macro=30_000),
+    dict(alpha=-0.2, wce=1.0, n1=32, n2=64, x1_out=-0.3, kappa=0.7, mi=25.0, Ti=1.0, n_macro=10_000),
+    dict(alpha=0.1, wce=0.0, n1=16, n2=16, x1_out=-0.1, kappa=3.0, mi=100.0, Ti=1.0, n_macro=5_000),
+]
+
+
+def _shape(e):
+    return (e["n2"] + 1, e["n1"] + 1)
+
+
+def _dev_cfg(e, seed=SEED, n_macro=None, weight=0.0):
+    n = e["n_macro"] if n_macro is None else n_macro
+    sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, weight, n),
+          apic.species(1.0, e["mi"], e["Ti"], 1.0, 0.0, weight, n)]
+    return apic.grain_cfg(e["alpha"], e["n1"], e["n2"], sp, x1_out=e["x1_out"], wce=e["wce"],
+                          kappa=e["kappa"], phi_grain=-2.5, phi_out=0.0, dt=0.05, seed=seed)
+
+
+def _oracle(e, g, frozen, inject, n_macro=None, weight=0.0):
+    n = e["n_macro"] if n_macro is None else n_macro
+    cfg = Config(alpha=e["alpha"], n1=e["n1"], n2=e["n2"], x1_out=e["x1_out"], wce=e["wce"],
+                 kappa=e["kappa"], dt=0.05, seed=SEED, grain=g,
+                 species=[Species(q=-1.0, m=1.0, T=1.0, n=1.0, n_macro=n, weight=weight),
+                          Species(q=1.0, m=e["mi"], T=e["Ti"], n=1.0, n_macro=n, weight=weight)])
+    sim = Simulation(cfg)
+    sim.frozen = frozen
+    sim.inject_enabled = inject
+    return sim
+
+
+def test_ensemble_poisson_matches_oracle():
+    ctx = apic.apic_init([_dev_cfg(e) for e in ENSEMBLE], apic.opts(precision=FP64, inject=False))
+    try:
+        for g, e in enumerate(ENSEMBLE):
+            rho = smooth_density(e["n1"], e["n2"], seed=30 + g, amplitude=1.0)
+            phi = apic.apic_solve_poisson(ctx, g, rho, shape=_shape(e))
+            sim = _oracle(e, g, True, False)
+            ref = sim.solver.solve(source_from_density(rho, e["kappa"]), -2.5, 0.0)
+            rel = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+            print(f"grain {g} grid {e['n1']}x{e['n2']} phi rel {rel:.2e}", flush=True)
+            assert rel < 1e-10
+    finally:
+        apic.apic_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_ensemble_frozen_push_matches_oracle(precision):
+    """Each grain of the ensemble against its own oracle run: frozen field from a
+    given density, 50 steps with injection, per-particle state by id."""
+    cfgs = [_dev_cfg(e, n_macro=0, weight=0.02) for e in ENSEMBLE]
+    ctx = apic.apic_init(cfgs, apic.opts(precision=precision, inject=True, frozen_field=True))
+    sims = []
+    n = 2000
+    try:
+        for g, e in enumerate(ENSEMBLE):
+            sim = _oracle(e, g, True, True, n_macro=0, weight=0.02)
+            rho = smooth_density(e["n1"], e["n2"], seed=40 + g, amplitude=1.0)
+            apic.apic_solve_poisson(ctx, g, rho, shape=_shape(e))
+            sim.set_phi(sim.solver.solve(source_from_density(rho, e["kappa"]), -2.5, 0.0))
+            for s, vs in ((0, 1.0), (1, 0.2)):
+                parts = random_particles(n, e["x1_out"], seed=50 + 2 * g + s, v_sigma=vs)
+                apic.apic_inject(ctx, g, s, *parts)
+                sim.set_particles(s, *parts)
+            sims.append(sim)
+        apic.apic_step(ctx, 50)
+        for g, (e, sim) in enumerate(zip(ENSEMBLE, sims)):
+            sim.run(50)
+            t = apic.apic_tallies(ctx, g, 2, e["n2"])
+            for s, vs in ((0, 1.0), (1, 0.2)):
+                assert int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
+                assert int(t["injected"][s]) == int(sim.injected[s]) + n
+                dev = apic.apic_particles(ctx, g, s, int(t["resident"][s]) + 10)
+                ora = sim.particles(s)
+                err, common = particle_error(dev, ora, sim.grid, vs)
+                mismatch = len(dev["id"]) + len(ora["id"]) - 2 * common
+                print(f"grain {g} s={s} live {len(ora['id'])} median {np.median(err):.2e} "
+                      f"q99.9 {np.quantile(err, 0.999):.2e} mismatch {mismatch}", flush=True)
+                if precision == FP64:
+                    assert mismatch <= max(1, len(ora["id"]) // 1000)
+                    assert np.quantile(err, 0.999) < 1e-9
+                else:
+                    assert mismatch <= max(2, len(ora["id"]) // 200)
+                    assert np.median(err) < 1e-5
+    finally:
+        apic.apic_free(ctx)
+
+
+def test_ensemble_matches_one_grain_contexts():
+    """Self-consistent FP64 runs: every grain of the ensemble against the same
+    grain alone in its own context (Philox key shifted to the grain's), 40
+    steps with volume load and injection."""
+    steps = 40
+    ctx = apic.apic_init([_dev_cfg(e) for e in ENSEMBLE], apic.opts(precision=FP64, inject=True))
+    try:
+        for g in range(len(ENSEMBLE)):
+            for s in range(2):
+                apic.apic_inject(ctx, g, s)
+        apic.apic_step(ctx, steps)
+        for g, e in enumerate(ENSEMBLE):
+            solo = apic.apic_init([_dev_cfg(e, seed=SEED + (g << 32))], apic.opts(precision=FP64, inject=True))
+            try:
+                for s in range(2):
+                    apic.apic_inject(solo, 0, s)
+                apic.apic_step(solo, steps)
+                ta = apic.apic_tallies(ctx, g, 2, e["n2"])
+                tb = apic.apic_tallies(solo, 0, 2, e["n2"])
+                pa, _ = apic.apic_fields(ctx, g, _shape(e))
+                pb, _ = apic.apic_fields(solo, 0, _shape(e))
+            finally:
+                apic.apic_free(solo)
+            rel = np.max(np.abs(pa - pb)) / np.max(np.abs(pb))
+            print(f"grain {g}: absorbed {list(ta['absorbed'])} vs {list(tb['absorbed'])}, "
+                  f"escaped {list(ta['escaped'])} vs {list(tb['escaped'])}, phi rel {rel:.1e}", flush=True)
+            for s in range(2):
+                assert int(ta["injected"][s]) == int(tb["injected"][s])
+                assert int(ta["injected"][s]) == int(ta["absorbed"][s] + ta["escaped"][s] + ta["resident"][s])
+                for k in ("absorbed", "escaped"):
+                    a, b = int(ta[k][s]), int(tb[k][s])
+                    assert abs(a - b) <= max(3, 0.01 * b)
+            assert rel < 1e-6
+    finally:
+        apic.apic_free(ctx)
+
+
+def test_autotuned_schedule_gives_the_same_particles():
+    """The autotuner changes launch shapes, sort tiles and the sort interval
+    only: in a frozen field the particles of a tuned and an untuned context are
+    bit-identical after the same steps."""
+    cfgs = [_dev_cfg(e, n_macro=0, weight=0.02) for e in ENSEMBLE[:3]]
+    ctxs = [apic.apic_init(cfgs, apic.opts(precision=FP32, inject=True, frozen_field=True, autotune=a))
+            for a in (False, True)]
+    try:
+        for ctx in ctxs:
+            for g, e in enumerate(ENSEMBLE[:3]):
+                rho = smooth_density(e["n1"], e["n2"], seed=60 + g, amplitude=1.0)
+                apic.apic_solve_poisson(ctx, g, rho, shape=_shape(e))
+                for s, vs in ((0, 1.0), (1, 0.2)):
+                    apic.apic_inject(ctx, g, s, *random_particles(3000, e["x1_out"], seed=70 + 2 * g + s,
+                                                                  v_sigma=vs))
+            apic.apic_step(ctx, 15)
+            apic.apic_step(ctx, 25)     # tuning continues across calls
+        sched = apic.apic_schedule(ctxs[1])
+        print("schedule", sched, flush=True)
+        assert sched["tuned"] == 1
+        assert 1 <= sched["push_wg_per_cu"] <= 8
+        assert sched["tile_log2"] in (2, 3, 4)
+        assert 1 <= sched["sort_every"] <= 16
+        for g, e in enumerate(ENSEMBLE[:3]):
+            ta = apic.apic_tallies(ctxs[0], g, 2, e["n2"])
+            tb = apic.apic_tallies(ctxs[1], g, 2, e["n2"])
+            for s in range(2):
+                for k in ("injected", "absorbed", "escaped", "resident"):
+                    assert int(ta[k][s]) == int(tb[k][s])
+                pa = apic.apic_particles(ctxs[0], g, s, int(ta["resident"][s]) + 10)
+                pb = apic.apic_particles(ctxs[1], g, s, int(tb["resident"][s]) + 10)
+                for k in ("id", "x1", "x2", "vR", "vZ", "vT"):
+                    assert np.array_equal(pa[k], pb[k])
+                assert np.allclose(ta["charge"][s], tb["charge"][s], rtol=1e-12, atol=0)
+    finally:
+        for ctx in ctxs:
+            apic.apic_free(ctx)
