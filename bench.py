@@ -8,7 +8,11 @@ both species pushed per step, summed, divided by the wall time between two
 device synchronisations), inputs resident in HBM before timing starts.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-[--workload c3] [--no-fp64] [--no-cpu-baseline]
+[--workload c3] [--no-fp64] [--no-cpu-baseline] [--no-ensemble]
+
+Beside the headline workload the line carries the plain FP64 path on the same
+workload (`fp64`), the 64-grain ensemble in one context (`ensemble`), and the
+oracle's rate on a bounded sample (`cpu_baseline`).
 """
 import argparse
 import json
@@ -57,21 +61,32 @@ def measured_traffic(particles_per_launch):
     return float(vals["hbm_bytes_per_particle_step"]) * particles_per_launch
 
 
-def run_gpu(w, precision, steps, warmup, stream):
+def grain_cfgs(grains):
+    import paper_2307_11107_amd as apic
+    cfgs = []
+    for w in grains:
+        sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]),
+              apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])]
+        cfgs.append(apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"],
+                                   kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"]))
+    return cfgs
+
+
+def run_gpu(grains, precision, steps, warmup, stream, autotune=False):
+    """Loads every grain, runs `warmup` steps (the autotuner's steps among
+    them), then times `steps` steps between device synchronisations."""
     import torch
     import paper_2307_11107_amd as apic
-    sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]),
-          apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])]
-    cfg = apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"],
-                         kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"])
     prec = apic.APIC_FP32_SPLIT if precision == "fp32" else apic.APIC_FP64
-    ctx = apic.apic_init([cfg], apic.opts(precision=prec, inject=True, stream=stream))
+    ctx = apic.apic_init(grain_cfgs(grains), apic.opts(precision=prec, inject=True, stream=stream,
+                                                       autotune=autotune))
     try:
-        for s in range(2):
-            apic.apic_inject(ctx, 0, s)
+        for g in range(len(grains)):
+            for s in range(2):
+                apic.apic_inject(ctx, g, s)
         apic.apic_step(ctx, warmup)
         torch.cuda.synchronize()
-        t0 = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        t0 = [apic.apic_tallies(ctx, g, 2, w["n2"]) for g, w in enumerate(grains)]
         apic.apic_set_profiling(ctx, True)
         torch.cuda.synchronize()
         start = time.perf_counter()
@@ -79,14 +94,15 @@ def run_gpu(w, precision, steps, warmup, stream):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - start
         tm = apic.apic_timing(ctx)
-        t1 = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        t1 = [apic.apic_tallies(ctx, g, 2, w["n2"]) for g, w in enumerate(grains)]
+        sched = apic.apic_schedule(ctx)
     finally:
         apic.apic_free(ctx)
-    pushed = int(sum(t1["particle_steps"]) - sum(t0["particle_steps"]))
-    return {"elapsed": elapsed, "particle_steps": pushed, "timing": tm,
-            "resident": [int(x) for x in t1["resident"]],
-            "balance_exact": all(int(t1["injected"][s]) == int(t1["absorbed"][s] + t1["escaped"][s] + t1["resident"][s])
-                                 for s in range(2))}
+    pushed = int(sum(sum(b["particle_steps"]) - sum(a["particle_steps"]) for a, b in zip(t0, t1)))
+    balance = all(int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
+                  for t in t1 for s in range(2))
+    return {"elapsed": elapsed, "particle_steps": pushed, "timing": tm, "balance_exact": balance,
+            "schedule": sched}
 
 
 def cpu_baseline(w, n_sample, steps):
@@ -120,19 +136,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--ensemble-warmup", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the particle loop of this build runs on a single MI355X "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
-    from synthetic_inputs import WORKLOADS
+    from synthetic_inputs import WORKLOADS, ensemble_c4
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     copy_calibration()
 
-    r32 = run_gpu(w, "fp32", args.steps, args.warmup, stream)
+    r32 = run_gpu([w], "fp32", args.steps, args.warmup, stream)
     value = r32["particle_steps"] / r32["elapsed"]
     tm = r32["timing"]
     push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
@@ -165,7 +184,7 @@ def main():
         "balance_exact": r32["balance_exact"],
     }
     if not args.no_fp64:
-        r64 = run_gpu(w, "fp64", args.steps, args.warmup, stream)
+        r64 = run_gpu([w], "fp64", args.steps, args.warmup, stream)
         v64 = r64["particle_steps"] / r64["elapsed"]
         t64 = r64["timing"]
         a64 = t64["push_ms"] / max(t64["push_launches"], 1)
@@ -174,6 +193,24 @@ def main():
                        "push_GBps": BYTES_PER_PARTICLE["fp64"] * r64["particle_steps"] / max(t64["push_launches"], 1)
                        / (a64 * 1e-3) / 1e9}
         out["speedup_fp32_vs_fp64"] = value / v64
+    if not args.no_ensemble:
+        ens = ensemble_c4()
+        re = run_gpu(ens, "fp32", args.ensemble_steps, args.ensemble_warmup, stream, autotune=True)
+        te = re["timing"]
+        pe = te["push_ms"] / max(te["push_launches"], 1)
+        ve = re["particle_steps"] / re["elapsed"]
+        gbe = BYTES_PER_PARTICLE["fp32"] * re["particle_steps"] / max(te["push_launches"], 1) / (pe * 1e-3) / 1e9
+        out["ensemble"] = {
+            "workload": f"c4: {len(ens)} grains in one context (alpha U[0,0.2], wce/wpe in {{0,0.5,1}}, "
+                        f"lambdaD/R0 U[0.5,5], grids 128x128..512x256, "
+                        f"{sum(g['n_macro'] for g in ens):.3g} macro-particles per species in total, "
+                        f"log-uniform 1e6-2e7 per grain), FP32 split, autotuned schedule, graph-captured steps",
+            "value": ve, "unit": "particle-steps/s", "ms_per_step": 1e3 * re["elapsed"] / args.ensemble_steps,
+            "push_avg_launch_ms": pe, "push_GBps": gbe, "push_frac_of_hbm_peak": gbe / HBM_PEAK_GBS,
+            "breakdown_ms_per_step": {k: te[k] / max(te["steps"], 1)
+                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+            "mg_cycles_per_step": te["mg_cycles"] / max(te["steps"], 1),
+            "schedule": re["schedule"], "balance_exact": re["balance_exact"]}
     if not args.no_cpu_baseline:
         rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

@@ -135,13 +135,14 @@ class Simulation:
         z = np.zeros(0)
         return {"x1": z, "x2": z, "vR": z, "vZ": z, "vT": z, "id": np.zeros(0, dtype=np.int64)}
 
-    def set_particles(self, s, x1, x2, vR, vZ, vT):
-        """Explicit particles (ids 0..n-1), replacing species s."""
+    def set_particles(self, s, x1, x2, vR, vZ, vT, ids=None):
+        """Explicit particles (ids 0..n-1 unless given), replacing species s."""
         n = len(x1)
+        idv = np.arange(n, dtype=np.int64) if ids is None else np.array(ids, dtype=np.int64)
         self.parts[s] = {"x1": np.array(x1, dtype=np.float64), "x2": np.array(x2, dtype=np.float64),
                          "vR": np.array(vR, dtype=np.float64), "vZ": np.array(vZ, dtype=np.float64),
-                         "vT": np.array(vT, dtype=np.float64), "id": np.arange(n, dtype=np.int64)}
-        self.next_id[s] = n
+                         "vT": np.array(vT, dtype=np.float64), "id": idv}
+        self.next_id[s] = int(idv.max()) + 1 if n else 0
 
     def particles(self, s):
         """Copy of species s sorted by particle id."""
@@ -153,12 +154,15 @@ class Simulation:
         return len(self.parts[s]["x1"])
 
     # ------------------------------------------------------------------ load
-    def load(self, s, n=None):
-        """Initial volume load of species s (n defaults to n_macro)."""
+    def load(self, s, n=None, slots=None):
+        """Initial volume load of species s (n defaults to n_macro).  With
+        `slots`, only the particles of those load indices are drawn (each
+        particle's draws depend on its own index alone), with ids = slots."""
         sp = self.cfg.species[s]
         n = sp.n_macro if n is None else n
         a, xo = self.cfg.alpha, self.cfg.x1_out
-        slot = np.arange(n, dtype=np.uint64)
+        slot = np.arange(n, dtype=np.uint64) if slots is None else np.asarray(slots, dtype=np.uint64)
+        n = len(slot)
         x2 = np.zeros(n)
         r3 = np.zeros(n)
         todo = np.ones(n, dtype=bool)
@@ -183,7 +187,7 @@ class Simulation:
         vR = sig * g0 * np.cos(2.0 * np.pi * to_unit(u1))
         vZ = sig * g0 * np.sin(2.0 * np.pi * to_unit(u1))
         vT = sig * g1 * np.cos(2.0 * np.pi * to_unit(u3))
-        self.set_particles(s, x1, x2, vR, vZ, vT)
+        self.set_particles(s, x1, x2, vR, vZ, vT, ids=None if slots is None else slot.astype(np.int64))
 
     # ------------------------------------------------------------------ field
     def deposit(self, x1, x2):

@@ -616,11 +616,14 @@ int build_tables(apic_ctx* ctx) {
             d.nn = l == 0 ? g.axis_nn : nullptr;
             d.ss = l == 0 ? g.axis_ss : nullptr;
             d.inv = d.coarsest ? g.coarse_inv : nullptr;
-            ctx->lvl_max_n1[l] = std::max(ctx->lvl_max_n1[l], L.n1);
-            ctx->lvl_max_n2[l] = std::max(ctx->lvl_max_n2[l], L.n2);
             ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
-            if (!d.coarsest) ctx->lvl_lines_x2[l] += L.n1 / 2;
-            else ctx->lvl_max_m[l] = std::max(ctx->lvl_max_m[l], d.m);
+            if (!d.coarsest) {
+                ctx->lvl_max_n1[l] = std::max(ctx->lvl_max_n1[l], L.n1);
+                ctx->lvl_max_n2[l] = std::max(ctx->lvl_max_n2[l], L.n2);
+                ctx->lvl_lines_x2[l] += L.n1 / 2;
+            } else {
+                ctx->lvl_max_m[l] = std::max(ctx->lvl_max_m[l], d.m);
+            }
         }
     TRY(alloc_t(ctx, &ctx->mgdesc, ctx->mgdesc_h.size()));
     HIPCHK(ctx, hipMemcpy(ctx->mgdesc, ctx->mgdesc_h.data(), sizeof(MGDesc) * ctx->mgdesc_h.size(),
@@ -645,9 +648,19 @@ int apply_tiles(apic_ctx* ctx, int t) {
 }
 
 int sort_all(apic_ctx* ctx) {
-    TRY(run_phase(ctx, G_SORT, [&] { (void)launch_sort(ctx); }));
+    TRY(run_phase(ctx, G_SORT, [&] { (void)launch_sort(ctx, 0, ctx->ntasks); }));
     for (auto& g : ctx->grains)
         for (int s = 0; s < g.ns; ++s) g.cur[s] = 1 - g.cur[s];
+    return APIC_OK;
+}
+
+// sort of one (grain, species) task, outside the step graphs
+int sort_one(apic_ctx* ctx, int grain, int s) {
+    int t = 0;
+    while (t < ctx->ntasks && !(ctx->tasks_h[t].grain == grain && ctx->tasks_h[t].s == s)) ++t;
+    if (t == ctx->ntasks) return fail(ctx, APIC_EINVAL, "no such task");
+    HIPCHK(ctx, launch_sort(ctx, t, 1));
+    ctx->grains[grain].cur[s] = 1 - ctx->grains[grain].cur[s];
     return APIC_OK;
 }
 
@@ -965,7 +978,7 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
                                 sizeof(double) * g.gp.n_bins));
     HIPCHK(ctx, launch_fill(ctx, g.tally_count + (size_t)s * g.gp.n_bins,
                             sizeof(unsigned long long) * g.gp.n_bins));
-    TRY(sort_all(ctx));
+    TRY(sort_one(ctx, grain, s));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     g.field_stale = true;
     return APIC_OK;

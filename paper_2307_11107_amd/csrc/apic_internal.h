@@ -254,7 +254,7 @@ namespace apic {
 hipError_t launch_push(apic_ctx* ctx, bool deposit);
 hipError_t launch_deposit(apic_ctx* ctx);
 hipError_t launch_inject(apic_ctx* ctx, bool deposit);
-hipError_t launch_sort(apic_ctx* ctx);
+hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks);
 hipError_t launch_load(apic_ctx* ctx, Grain& g, int s, int64_t n);
 hipError_t launch_set_particles(apic_ctx* ctx, Grain& g, int s, int64_t n, const double* dx1,
                                 const double* dx2, const double* dvR, const double* dvZ,

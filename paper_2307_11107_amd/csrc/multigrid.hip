@@ -592,4 +592,5 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
     return hipGetLastError();
 }
 
+
 }  // namespace apic

@@ -1371,6 +1371,55 @@ k_scan_apply(const PushTask* __restrict__ tasks) {
     }
 }
 
+// One particle's slot contents, moved as a unit by the scatter.
+struct Moved {
+    uint32_t w[5];      // FP32: cell, f1, f2, vR, vZ bits; FP64: unused
+    uint32_t vT;
+    uint64_t d[5];      // FP64: x1, x2, vR, vZ, vT bits
+    uint32_t id;
+};
+
+__device__ inline void load_moved(bool split, const PBuf& b, int64_t p, Moved& m) {
+    if (split) {
+        m.w[0] = static_cast<const uint32_t*>(b.pos0)[p];
+        m.w[1] = static_cast<const uint32_t*>(b.pos1)[p];
+        m.w[2] = static_cast<const uint32_t*>(b.pos2)[p];
+        m.w[3] = static_cast<const uint32_t*>(b.vR)[p];
+        m.w[4] = static_cast<const uint32_t*>(b.vZ)[p];
+        m.vT = static_cast<const uint32_t*>(b.vT)[p];
+    } else {
+        m.d[0] = static_cast<const uint64_t*>(b.pos1)[p];
+        m.d[1] = static_cast<const uint64_t*>(b.pos2)[p];
+        m.d[2] = static_cast<const uint64_t*>(b.vR)[p];
+        m.d[3] = static_cast<const uint64_t*>(b.vZ)[p];
+        m.d[4] = static_cast<const uint64_t*>(b.vT)[p];
+    }
+    m.id = b.id[p];
+}
+
+__device__ inline void store_moved(bool split, const PBuf& b, int64_t o, const Moved& m) {
+    if (split) {
+        static_cast<uint32_t*>(b.pos0)[o] = m.w[0];
+        static_cast<uint32_t*>(b.pos1)[o] = m.w[1];
+        static_cast<uint32_t*>(b.pos2)[o] = m.w[2];
+        static_cast<uint32_t*>(b.vR)[o] = m.w[3];
+        static_cast<uint32_t*>(b.vZ)[o] = m.w[4];
+        static_cast<uint32_t*>(b.vT)[o] = m.vT;
+    } else {
+        static_cast<uint64_t*>(b.pos1)[o] = m.d[0];
+        static_cast<uint64_t*>(b.pos2)[o] = m.d[1];
+        static_cast<uint64_t*>(b.vR)[o] = m.d[2];
+        static_cast<uint64_t*>(b.vZ)[o] = m.d[3];
+        static_cast<uint64_t*>(b.vT)[o] = m.d[4];
+    }
+    b.id[o] = m.id;
+}
+
+// Scatter: SCATTER_BATCHES batches of BLOCK particles per iteration, all their
+// loads issued before the LDS cursor updates, so the slot range streams at
+// full memory parallelism.
+constexpr int SCATTER_BATCHES = 8;
+
 __global__ void __launch_bounds__(BLOCK)
 k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
     extern __shared__ int cur[];
@@ -1387,31 +1436,25 @@ k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
     const int lane = threadIdx.x & 63;
     int64_t lo, hi;
     sort_range(T.ctr->n[T.s], SB, lo, hi);
-    for (int64_t base = lo; base < hi; base += BLOCK) {
-        const int64_t p = base + threadIdx.x;
-        const int key = p < hi ? tile_key(gp, split, src, p) : -1;
-        int head, len;
-        bool is_head;
-        wave_runs(key, head, len, is_head);
-        int start = 0;
-        if (is_head && key >= 0) start = atomicAdd(&cur[key], len);
-        const int64_t o = (int64_t)__shfl(start, head) + (lane - head);
-        if (key < 0) continue;
-        if (split) {
-            static_cast<int32_t*>(dst.pos0)[o] = static_cast<const int32_t*>(src.pos0)[p];
-            static_cast<float*>(dst.pos1)[o] = static_cast<const float*>(src.pos1)[p];
-            static_cast<float*>(dst.pos2)[o] = static_cast<const float*>(src.pos2)[p];
-            static_cast<float*>(dst.vR)[o] = static_cast<const float*>(src.vR)[p];
-            static_cast<float*>(dst.vZ)[o] = static_cast<const float*>(src.vZ)[p];
-            static_cast<float*>(dst.vT)[o] = static_cast<const float*>(src.vT)[p];
-        } else {
-            static_cast<double*>(dst.pos1)[o] = static_cast<const double*>(src.pos1)[p];
-            static_cast<double*>(dst.pos2)[o] = static_cast<const double*>(src.pos2)[p];
-            static_cast<double*>(dst.vR)[o] = static_cast<const double*>(src.vR)[p];
-            static_cast<double*>(dst.vZ)[o] = static_cast<const double*>(src.vZ)[p];
-            static_cast<double*>(dst.vT)[o] = static_cast<const double*>(src.vT)[p];
+    for (int64_t base = lo; base < hi; base += SCATTER_BATCHES * BLOCK) {
+        Moved m[SCATTER_BATCHES];
+        int key[SCATTER_BATCHES];
+#pragma unroll
+        for (int k = 0; k < SCATTER_BATCHES; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            key[k] = p < hi ? tile_key(gp, split, src, p) : -1;
+            if (p < hi) load_moved(split, src, p, m[k]);
         }
-        dst.id[o] = src.id[p];
+#pragma unroll
+        for (int k = 0; k < SCATTER_BATCHES; ++k) {
+            int head, len;
+            bool is_head;
+            wave_runs(key[k], head, len, is_head);
+            int start = 0;
+            if (is_head && key[k] >= 0) start = atomicAdd(&cur[key[k]], len);
+            const int64_t o = (int64_t)__shfl(start, head) + (lane - head);
+            if (key[k] >= 0) store_moved(split, dst, o, m[k]);
+        }
     }
 }
 
@@ -1506,17 +1549,18 @@ hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
     return hipGetLastError();
 }
 
-hipError_t launch_sort(apic_ctx* ctx) {
+hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks) {
     const bool split = is_split(ctx);
     const size_t lds = sizeof(int) * (size_t)ctx->max_ntiles;
-    const dim3 sgrid(ctx->max_sort_blocks, ctx->ntasks);
-    const dim3 cgrid(ctx->max_segs, ctx->ntasks);
-    hipLaunchKernelGGL(k_tile_hist, sgrid, dim3(BLOCK), lds, ctx->stream, ctx->tasks, split);
-    hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, ctx->tasks);
-    hipLaunchKernelGGL(k_scan_segs, dim3(ctx->ntasks), dim3(1024), 0, ctx->stream, ctx->tasks);
-    hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, ctx->tasks);
-    hipLaunchKernelGGL(k_tile_scatter, sgrid, dim3(BLOCK), lds, ctx->stream, ctx->tasks, split);
-    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks);
+    const PushTask* t = ctx->tasks + first_task;
+    const dim3 sgrid(ctx->max_sort_blocks, n_tasks);
+    const dim3 cgrid(ctx->max_segs, n_tasks);
+    hipLaunchKernelGGL(k_tile_hist, sgrid, dim3(BLOCK), lds, ctx->stream, t, split);
+    hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, t);
+    hipLaunchKernelGGL(k_scan_segs, dim3(n_tasks), dim3(1024), 0, ctx->stream, t);
+    hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, t);
+    hipLaunchKernelGGL(k_tile_scatter, sgrid, dim3(BLOCK), lds, ctx->stream, t, split);
+    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, t, n_tasks);
     return hipGetLastError();
 }
 

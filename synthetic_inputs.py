@@ -13,7 +13,11 @@ measured on (the paper itself gives no run sizes; see the design notes):
   c3  alpha = 0.2, omega_ce/omega_pe = 1, 512 x 512, mi/me = 1836, Ti/Te = 0.5,
       lambda_D/R0 = 1, 5e7 per species, 2000 steps;
   c5  alpha = 0.2, omega_ce/omega_pe = 2, 2048 x 1024, x1_out = -0.02,
-      mi/me = 1836, Te = Ti, lambda_D/R0 = 5, 2e8 per species, 1000 steps.
+      mi/me = 1836, Te = Ti, lambda_D/R0 = 5, 2e8 per species, 1000 steps;
+  c4  an ensemble of 64 grains (ensemble_c4): alpha uniform in [0, 0.2],
+      omega_ce/omega_pe in {0, 0.5, 1}, lambda_D/R0 uniform in [0.5, 5], grids
+      128 x 128, 256 x 128, 256 x 256 or 512 x 256, 1e6 - 2e7 macro-particles
+      per species (log-uniform), mi/me = 1836, Te = Ti, x1_out = -0.1, 1000 steps.
 """
 import numpy as np
 
@@ -27,6 +31,23 @@ WORKLOADS = {
     "c5": dict(alpha=0.2, wce=2.0, n1=2048, n2=1024, x1_out=-0.02, kappa=5.0, mi=1836.0, Ti=1.0,
                n_macro=200_000_000, steps=1000, dt=0.05, seed=0),
 }
+
+C4_GRIDS = [(128, 128), (256, 128), (256, 256), (512, 256)]
+
+
+def ensemble_c4(n_grains=64, particle_scale=1.0, seed=0):
+    """The grains of the c4 ensemble, drawn from a seeded generator; particle
+    counts can be scaled down (particle_scale < 1) for tests."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(n_grains):
+        n1, n2 = C4_GRIDS[int(rng.integers(0, len(C4_GRIDS)))]
+        n = float(np.exp(rng.uniform(np.log(1e6), np.log(2e7))))
+        out.append(dict(alpha=float(rng.uniform(0.0, 0.2)), wce=float(rng.choice([0.0, 0.5, 1.0])),
+                        n1=n1, n2=n2, x1_out=-0.1, kappa=float(rng.uniform(0.5, 5.0)), mi=1836.0, Ti=1.0,
+                        n_macro=max(1, int(n * particle_scale)), steps=1000, dt=0.05, seed=0))
+    return out
+
 
 PHI_GRAIN = -2.5
 PHI_OUT = 0.0

@@ -1,0 +1,87 @@
+"""Full-size runs in the configuration the benchmark times: the c3 workload
+(alpha = 0.2, omega_ce/omega_pe = 1, 512 x 512 cells, 5e7 macro-particles per
+species, injection, deposit, FP64 multigrid, sort), one full step through the
+C ABI.  The oracle cannot run 1e8 particles, so sampled particles are checked
+one by one and the rest through properties that hold at any size:
+
+  * sampled load indices: the oracle draws those particles of the volume load
+    itself and advances them one step in the same potential (the potential of
+    the step is set from a given density and solved by the oracle's LU);
+  * every particle: exact bookkeeping, injected count = load + the
+    fixed-point accumulator's count, total deposited charge = sum q w N."""
+import numpy as np
+import pytest
+
+import paper_2307_11107_amd as apic
+from gpu_util import particle_error
+from oracle.pic import Config, Simulation, Species
+from oracle.poisson import source_from_density
+from synthetic_inputs import WORKLOADS, smooth_density
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = 20_000
+
+
+@pytest.mark.parametrize("precision", [apic.APIC_FP32_SPLIT, apic.APIC_FP64])
+def test_c3_full_size_step_on_sampled_particles(precision):
+    w = dict(WORKLOADS["c3"])
+    n = w["n_macro"]
+    print(f"c3 full size precision={precision} n={n}", flush=True)
+    sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, n), apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, n)]
+    cfg = apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"], kappa=w["kappa"],
+                         phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"])
+    shape = (w["n2"] + 1, w["n1"] + 1)
+    rho = smooth_density(w["n1"], w["n2"], seed=77, amplitude=0.5)
+    ocfg = Config(alpha=w["alpha"], n1=w["n1"], n2=w["n2"], x1_out=w["x1_out"], wce=w["wce"], kappa=w["kappa"],
+                  dt=w["dt"], seed=w["seed"],
+                  species=[Species(q=-1.0, m=1.0, T=1.0, n=1.0, n_macro=n),
+                           Species(q=1.0, m=w["mi"], T=w["Ti"], n=1.0, n_macro=n)])
+    sim = Simulation(ocfg)
+    sim.frozen = True
+    sim.inject_enabled = False
+    sim.set_phi(sim.solver.solve(source_from_density(rho, w["kappa"]), -2.5, 0.0))
+    rng = np.random.default_rng(5)
+    ids = [np.sort(rng.choice(n, SAMPLE, replace=False)) for _ in range(2)]
+    for s in range(2):
+        sim.load(s, slots=ids[s])
+    sim.step()
+
+    ctx = apic.apic_init([cfg], apic.opts(precision=precision, inject=True))
+    try:
+        for s in range(2):
+            apic.apic_inject(ctx, 0, s)
+        # the first step pushes in the potential of the given density
+        apic.apic_solve_poisson(ctx, 0, rho, shape=shape)
+        apic.apic_step(ctx, 1)
+        t = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        _, rho_dep = apic.apic_fields(ctx, 0, shape)
+        total = 0.0
+        for s, vs in ((0, 1.0), (1, np.sqrt(w["Ti"] / w["mi"]))):
+            res = int(t["resident"][s])
+            assert int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
+            inj_step = (sim.inj_inc[s] >> 32)
+            assert int(t["injected"][s]) == n + inj_step
+            dev = apic.apic_particles(ctx, 0, s, res + 16)
+            keep = np.isin(dev["id"], ids[s])
+            sub = {k: v[keep] for k, v in dev.items()}
+            ora = sim.particles(s)
+            err, common = particle_error(sub, ora, sim.grid, vs)
+            mismatch = len(sub["id"]) + len(ora["id"]) - 2 * common
+            print(f"s={s} resident {res} sampled {len(ora['id'])} median {np.median(err):.2e} "
+                  f"q99.9 {np.quantile(err, 0.999):.2e} max {err.max():.2e} mismatch {mismatch}", flush=True)
+            assert mismatch <= 2
+            if precision == apic.APIC_FP64:
+                assert np.quantile(err, 0.999) < 1e-10
+            else:
+                assert np.median(err) < 1e-6
+                assert np.quantile(err, 0.999) < 1e-5
+            total += sp[s].q * float(t["weight"][s]) * res
+        # charge of the deposit of the resident particles (node volumes from eq. 5)
+        vol = sim.vol
+        q_dep = float(np.sum(rho_dep * vol))
+        rel = abs(q_dep - total) / (float(t["weight"][0]) * n)
+        print(f"deposited charge {q_dep:.6e} expected {total:.6e} rel {rel:.2e}", flush=True)
+        assert rel < (1e-10 if precision == apic.APIC_FP64 else 1e-5)
+    finally:
+        apic.apic_free(ctx)
