@@ -258,8 +258,6 @@ void free_grain(Grain& g) {
     F(g.rho);
     F(g.tally);
     F(g.tally_count);
-    F(g.axis_nn);
-    F(g.axis_ss);
     F(g.coarse_inv);
     for (auto& L : g.mg) {
         F(L.st);
@@ -475,21 +473,17 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
         L.n2 = hs.levels[l].n2;
         L.nx = L.n1 + 1;
         L.nodes = L.nx * (L.n2 + 1);
-        TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
         TRY(alloc_t(ctx, &L.u, (size_t)L.nodes));
         TRY(alloc_t(ctx, &L.f, (size_t)L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.u, sizeof(double) * L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.f, sizeof(double) * L.nodes));
+        if (l == 0) continue;   // the finest operator is evaluated at the nodes
+        TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
         stage.resize((size_t)ST_COUNT * L.nodes);
         for (int k = 0; k < ST_COUNT; ++k)
             std::copy(hs.levels[l].c[k].begin(), hs.levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
         HIPCHK(ctx, hipMemcpy(L.st, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice));
     }
-    const int nx = g.gp.nx;
-    TRY(alloc_t(ctx, &g.axis_nn, (size_t)nx));
-    TRY(alloc_t(ctx, &g.axis_ss, (size_t)nx));
-    HIPCHK(ctx, hipMemcpy(g.axis_nn, hs.levels[0].nn.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(g.axis_ss, hs.levels[0].ss.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(g.coarse_inv, hs.inv.data(), sizeof(double) * hs.inv.size(), hipMemcpyHostToDevice));
     return APIC_OK;
 }
@@ -579,7 +573,6 @@ int build_tables(apic_ctx* ctx) {
         d.rho = g.rho;
         d.u = g.mg[0].u;
         d.f = g.mg[0].f;
-        d.diag = g.mg[0].st;
         d.grad = g.grad;
         d.ctr = g.ctr;
         ctx->n_levels = std::max(ctx->n_levels, (int)g.mg.size());
@@ -611,10 +604,11 @@ int build_tables(apic_ctx* ctx) {
             d.coarsest = l + 1 == (int)g.mg.size();
             d.m = d.coarsest ? g.coarse_nodes : 0;
             d.st = L.st;
+            d.alpha = g.gp.alpha;
+            d.h1 = g.gp.h1 * (double)(1 << l);
+            d.h2 = g.gp.h2 * (double)(1 << l);
             d.u = L.u;
             d.f = L.f;
-            d.nn = l == 0 ? g.axis_nn : nullptr;
-            d.ss = l == 0 ? g.axis_ss : nullptr;
             d.inv = d.coarsest ? g.coarse_inv : nullptr;
             ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
             if (!d.coarsest) {

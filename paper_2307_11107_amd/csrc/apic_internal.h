@@ -107,7 +107,6 @@ struct GrainDesc {
     double* rho;
     double* u;                  // phi (finest multigrid level)
     double* f;                  // right-hand side of the finest level
-    const double* diag;         // diagonal of the finest operator
     void* grad;
     DevCounters* ctr;
 };
@@ -117,11 +116,10 @@ struct MGDesc {
     int n1, n2, nx, nodes;
     int coarsest;               // this is the grain's last level (dense solve)
     int m;                      // nodes of the dense system (coarsest only)
-    const double* st;           // 9 stencil arrays [k * nodes + node]
+    double alpha, h1, h2;       // finest level: geometry of its stencil (evaluated at the nodes)
+    const double* st;           // coarse levels: 9 stencil arrays [k * nodes + node]
     double* u;
     double* f;
-    const double* nn;           // finest level: second-neighbour axis couplings
-    const double* ss;
     const double* inv;          // dense inverse (coarsest only)
 };
 
@@ -144,6 +142,7 @@ struct MGBatch {
 struct MGLevel {
     int n1, n2, nx, nodes;
     double* st = nullptr;       // 9 stencil arrays [k * nodes + node], k = C,W,E,S,N,SW,SE,NW,NE
+                                // (coarse levels; the finest level's is evaluated at the nodes)
     double* u = nullptr;        // solution (level 0: phi) / correction
     double* f = nullptr;        // right-hand side
 };
@@ -171,8 +170,6 @@ struct Grain {
     double* rho = nullptr;          // charge density of the last deposit
     double* tally = nullptr;        // [5][ns][n_bins]: charge, pR, pZ, L, energy
     unsigned long long* tally_count = nullptr;   // [ns][n_bins]
-    double* axis_nn = nullptr;      // level-0 second-neighbour coefficient on row i2 = 0
-    double* axis_ss = nullptr;      // ... on row i2 = n2
     double* coarse_inv = nullptr;   // dense inverse of the coarsest operator
     int coarse_nodes = 0;
     double bnd_norm2 = 0;           // |A_interior,boundary u_boundary|^2 (host)

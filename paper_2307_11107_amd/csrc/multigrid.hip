@@ -80,35 +80,98 @@ __device__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int
     }
 }
 
-struct StencilPtrs {
-    const double *C, *W, *E, *S, *N, *SW, *SE, *NW, *NE;
+// Coefficients of the 9-point operator at one unknown node (nn / ss: the
+// second-neighbour couplings of the axis rows of the finest level).
+struct Coef {
+    double C, W, E, S, N, SW, SE, NW, NE, nn, ss;
 };
 
-__host__ __device__ inline StencilPtrs stencil_ptrs(const double* st, int nodes) {
-    StencilPtrs p;
-    p.C = st + ST_C * (size_t)nodes;
-    p.W = st + ST_W * (size_t)nodes;
-    p.E = st + ST_E * (size_t)nodes;
-    p.S = st + ST_S * (size_t)nodes;
-    p.N = st + ST_N * (size_t)nodes;
-    p.SW = st + ST_SW * (size_t)nodes;
-    p.SE = st + ST_SE * (size_t)nodes;
-    p.NW = st + ST_NW * (size_t)nodes;
-    p.NE = st + ST_NE * (size_t)nodes;
-    return p;
-}
+// Coarse levels: the Galerkin stencil arrays.
+struct StoredStencil {
+    const double* st;
+    int nodes, n2;
+    __device__ explicit StoredStencil(const MGDesc& D) : st(D.st), nodes(D.nodes), n2(D.n2) {}
+    __device__ Coef at(int, int, size_t o) const {
+        const size_t n = (size_t)nodes;
+        Coef c;
+        c.C = st[ST_C * n + o];
+        c.W = st[ST_W * n + o];
+        c.E = st[ST_E * n + o];
+        c.S = st[ST_S * n + o];
+        c.N = st[ST_N * n + o];
+        c.SW = st[ST_SW * n + o];
+        c.SE = st[ST_SE * n + o];
+        c.NW = st[ST_NW * n + o];
+        c.NE = st[ST_NE * n + o];
+        c.nn = 0.0;
+        c.ss = 0.0;
+        return c;
+    }
+    __device__ double diag(int, int, size_t o) const { return st[ST_C * (size_t)nodes + o]; }
+};
 
-// (A u) at an unknown node (j, i) of a level; nn / ss carry the finest level's
-// second-neighbour axis couplings (null on coarse levels).
-__device__ inline double apply_A(const StencilPtrs& p, const double* __restrict__ nn,
-                                 const double* __restrict__ ss, const double* __restrict__ u, int n2,
-                                 int nx, int j, int i) {
+// Finest level: the central differences of eq. (7) evaluated at the node
+// (r from eq. 3, second-order one-sided d/dx2 on the axis rows), the same
+// expressions the host uses to build the hierarchy.  Nothing is read from
+// memory, which removes 72 bytes per node from every sweep of the largest
+// level.
+struct FineStencil {
+    double a, h1, h2, ih1sq, ih2sq, i2h2, i4h1h2;
+    int n2;
+    __device__ explicit FineStencil(const MGDesc& D)
+        : a(D.alpha), h1(D.h1), h2(D.h2), ih1sq(1.0 / (D.h1 * D.h1)), ih2sq(1.0 / (D.h2 * D.h2)),
+          i2h2(1.0 / (2.0 * D.h2)), i4h1h2(1.0 / (4.0 * D.h1 * D.h2)), n2(D.n2) {}
+    __device__ Coef at(int j, int i, size_t) const {
+        const double x1 = -1.0 + i * h1, x2 = -1.0 + j * h2;
+        const double r = -(1.0 + sqrt(1.0 - 4.0 * a * x1 * x2)) / (2.0 * x1);
+        const bool edge = (j == 0 || j == n2);
+        const double s2 = edge ? 0.0 : 1.0 - x2 * x2;
+        const double ir2 = 1.0 / (r * r);
+        const double t = r + 2.0 * a * x2;
+        const double a11 = (t * t + a * a * s2) * (ir2 * ir2 * ir2) * ih1sq;
+        const double c2 = -2.0 * x2 * ir2;
+        Coef c;
+        c.W = a11;
+        c.E = a11;
+        c.C = -2.0 * a11;
+        c.S = c.N = c.SW = c.SE = c.NW = c.NE = c.nn = c.ss = 0.0;
+        if (j == 0) {
+            const double b = c2 * i2h2;
+            c.C += -3.0 * b;
+            c.N = 4.0 * b;
+            c.nn = -b;
+        } else if (j == n2) {
+            const double b = c2 * i2h2;
+            c.C += 3.0 * b;
+            c.S = -4.0 * b;
+            c.ss = b;
+        } else {
+            const double a22 = s2 * ir2 * ih2sq;
+            const double b2 = c2 * i2h2;
+            const double a12 = -2.0 * a * s2 * (ir2 * ir2) * i4h1h2;
+            c.S = a22 - b2;
+            c.N = a22 + b2;
+            c.C += -2.0 * a22;
+            c.NE = a12;
+            c.SW = a12;
+            c.NW = -a12;
+            c.SE = -a12;
+        }
+        return c;
+    }
+    __device__ double diag(int j, int i, size_t o) const { return at(j, i, o).C; }
+};
+
+// (A u) at an unknown node (j, i) of a level.
+template <class ST>
+__device__ inline double apply_A(const ST& st, const double* __restrict__ u, int n2, int nx, int j, int i) {
     const size_t o = (size_t)j * nx + i;
-    double au = p.C[o] * u[o] + p.W[o] * u[o - 1] + p.E[o] * u[o + 1];
-    if (j > 0) au += p.S[o] * u[o - nx] + p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
-    if (j < n2) au += p.N[o] * u[o + nx] + p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
-    if (nn && j == 0) au += nn[i] * u[o + 2 * nx];
-    if (ss && j == n2) au += ss[i] * u[o - 2 * nx];
+    const Coef k = st.at(j, i, o);
+    double au = k.C * u[o] + k.W * u[o - 1] + k.E * u[o + 1];
+    if (j > 0) au += k.S * u[o - nx] + k.SW * u[o - nx - 1] + k.SE * u[o - nx + 1];
+    if (j < n2) au += k.N * u[o + nx] + k.NW * u[o + nx - 1] + k.NE * u[o + nx + 1];
+    if (j == 0) au += k.nn * u[o + 2 * nx];
+    if (j == n2) au += k.ss * u[o - 2 * nx];
     return au;
 }
 
@@ -125,7 +188,7 @@ __device__ inline int xcd_line() {
 }
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
-template <int K, int NT>
+template <int K, int NT, class ST>
 __global__ void __launch_bounds__(NT)
 k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
     extern __shared__ double lds[];
@@ -140,24 +203,23 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     double* c = b + L;
     double* d = c + L;
     const int nx = n1 + 1;
-    const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
-    const double* __restrict__ nn = D.nn;
-    const double* __restrict__ ss = D.ss;
+    const ST st(D);
     double* __restrict__ u = D.u;
     const double* __restrict__ f = D.f;
     for (int k = threadIdx.x; k < L; k += NT) {
         const int i = k + 1;
         const size_t o = (size_t)j * nx + i;
+        const Coef q = st.at(j, i, o);
         double rhs = f[o];
-        if (j > 0) rhs -= p.S[o] * u[o - nx] + p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
-        if (j < n2) rhs -= p.N[o] * u[o + nx] + p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
-        if (nn && j == 0) rhs -= nn[i] * u[o + 2 * nx];
-        if (ss && j == n2) rhs -= ss[i] * u[o - 2 * nx];
-        double aa = p.W[o], cc = p.E[o];
+        if (j > 0) rhs -= q.S * u[o - nx] + q.SW * u[o - nx - 1] + q.SE * u[o - nx + 1];
+        if (j < n2) rhs -= q.N * u[o + nx] + q.NW * u[o + nx - 1] + q.NE * u[o + nx + 1];
+        if (j == 0) rhs -= q.nn * u[o + 2 * nx];
+        if (j == n2) rhs -= q.ss * u[o - 2 * nx];
+        double aa = q.W, cc = q.E;
         if (i == 1) { rhs -= aa * u[o - 1]; aa = 0.0; }
         if (i == n1 - 1) { rhs -= cc * u[o + 1]; cc = 0.0; }
         a[k] = aa;
-        b[k] = p.C[o];
+        b[k] = q.C;
         c[k] = cc;
         d[k] = rhs;
     }
@@ -171,10 +233,11 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
 // that the row-wise loads stay within a cache line.  On the finest level the
 // axis rows carry a second-neighbour coupling (one-sided d/dx2); it is
 // eliminated with the adjacent row so each line stays tridiagonal.
-template <int K, int LPB, int NT>
+template <int K, int LPB, int NT, class ST>
 __global__ void __launch_bounds__(NT)
 k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
     extern __shared__ double lds[];
+    __shared__ double axis_nn[LPB], axis_ss[LPB];
     const MGDesc& D = lv[blockIdx.y];
     if (!level_active(D, ms)) return;
     const int n1 = D.n1, n2 = D.n2;
@@ -187,9 +250,7 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     double* c = b + total;
     double* d = c + total;
     const int nx = n1 + 1;
-    const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
-    const double* __restrict__ nn = D.nn;
-    const double* __restrict__ ss = D.ss;
+    const ST st(D);
     double* __restrict__ u = D.u;
     const double* __restrict__ f = D.f;
     for (int q = threadIdx.x; q < total; q += NT) {
@@ -204,30 +265,35 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
             continue;
         }
         const size_t o = (size_t)j * nx + i;
-        double rhs = f[o] - p.W[o] * u[o - 1] - p.E[o] * u[o + 1];
-        if (j > 0) rhs -= p.SW[o] * u[o - nx - 1] + p.SE[o] * u[o - nx + 1];
-        if (j < n2) rhs -= p.NW[o] * u[o + nx - 1] + p.NE[o] * u[o + nx + 1];
-        a[e] = j > 0 ? p.S[o] : 0.0;
-        b[e] = p.C[o];
-        c[e] = j < n2 ? p.N[o] : 0.0;
+        const Coef k = st.at(j, i, o);
+        double rhs = f[o] - k.W * u[o - 1] - k.E * u[o + 1];
+        if (j > 0) rhs -= k.SW * u[o - nx - 1] + k.SE * u[o - nx + 1];
+        if (j < n2) rhs -= k.NW * u[o + nx - 1] + k.NE * u[o + nx + 1];
+        a[e] = j > 0 ? k.S : 0.0;
+        b[e] = k.C;
+        c[e] = j < n2 ? k.N : 0.0;
         d[e] = rhs;
+        if (j == 0) axis_nn[m] = k.nn;
+        if (j == n2) axis_ss[m] = k.ss;
     }
     __syncthreads();
-    if (threadIdx.x < LPB && nn) {
+    if (threadIdx.x < LPB) {
         const int m = threadIdx.x, i = i0 + 2 * m;
-        if (i <= n1 - 1) {
+        const double g = axis_nn[m];
+        if (i <= n1 - 1 && g != 0.0) {
             const int e = m * L;
-            const double mm = nn[i] / c[e + 1];
+            const double mm = g / c[e + 1];
             b[e] -= mm * a[e + 1];
             c[e] -= mm * b[e + 1];
             d[e] -= mm * d[e + 1];
         }
     }
-    if (threadIdx.x >= 64 && threadIdx.x < 64 + LPB && ss) {
+    if (threadIdx.x >= 64 && threadIdx.x < 64 + LPB) {
         const int m = threadIdx.x - 64, i = i0 + 2 * m;
-        if (i <= n1 - 1) {
+        const double g = axis_ss[m];
+        if (i <= n1 - 1 && g != 0.0) {
             const int e = m * L + n2;
-            const double mm = ss[i] / a[e - 1];
+            const double mm = g / a[e - 1];
             a[e] -= mm * b[e - 1];
             b[e] -= mm * c[e - 1];
             d[e] -= mm * d[e - 1];
@@ -259,7 +325,7 @@ __device__ inline double block_sum(double v) {
 }
 
 // |D^-1 (f - A u)|^2 over the unknown nodes of the finest level (D = diagonal
-// of A): the operator's rows differ in scale by ~r^4, and the row-scaled norm
+// of A, lv = the finest level): the operator's rows differ in scale by ~r^4, and the row-scaled norm
 // weighs every node alike.  One partial sum per workgroup, part[grain][block];
 // the check adds them in a fixed order, so a solve is reproducible bit for bit.
 __global__ void __launch_bounds__(MG_BLOCK)
@@ -276,8 +342,14 @@ k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, d
     if (idx < D.nodes) {
         const int j = idx / nx, i = idx - j * nx;
         if (i > 0 && i < n1) {
-            const StencilPtrs p = stencil_ptrs(D.st, D.nodes);
-            const double q = (D.f[idx] - apply_A(p, D.nn, D.ss, D.u, n2, nx, j, i)) / p.C[idx];
+            const FineStencil st(D);
+            const Coef k = st.at(j, i, idx);
+            double au = k.C * D.u[idx] + k.W * D.u[idx - 1] + k.E * D.u[idx + 1];
+            if (j > 0) au += k.S * D.u[idx - nx] + k.SW * D.u[idx - nx - 1] + k.SE * D.u[idx - nx + 1];
+            if (j < n2) au += k.N * D.u[idx + nx] + k.NW * D.u[idx + nx - 1] + k.NE * D.u[idx + nx + 1];
+            if (j == 0) au += k.nn * D.u[idx + 2 * nx];
+            if (j == n2) au += k.ss * D.u[idx - 2 * nx];
+            const double q = (D.f[idx] - au) / k.C;
             rr = q * q;
         }
     }
@@ -300,7 +372,8 @@ k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double
     if (idx < D.nodes) {
         const int i = idx % nx;
         if (i > 0 && i < D.n1) {
-            const double q = D.f[idx] / D.st[ST_C * (size_t)D.nodes + idx];
+            const FineStencil st(D);
+            const double q = D.f[idx] / st.diag(idx / nx, i, idx);
             v = q * q;
         }
     }
@@ -378,6 +451,7 @@ k_mg_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int ngrai
 // fine residuals formed on the fly (full weighting without rows outside the
 // grid); fc = 0 on the coarse Dirichlet columns; the coarse correction uc is
 // cleared.
+template <class ST>
 __global__ void __launch_bounds__(MG_BLOCK)
 k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
                     const MGState* __restrict__ ms) {
@@ -394,7 +468,7 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
         C.f[idx] = 0.0;
         return;
     }
-    const StencilPtrs p = stencil_ptrs(F.st, F.nodes);
+    const ST st(F);
     double acc = 0.0;
     for (int dj = -1; dj <= 1; ++dj) {
         const int j = 2 * J + dj;
@@ -403,7 +477,7 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
         for (int di = -1; di <= 1; ++di) {
             const int i = 2 * I + di;      // 1 <= i <= n1f - 1
             const double wi = di == 0 ? 1.0 : 0.5;
-            const double r = F.f[(size_t)j * nxf + i] - apply_A(p, F.nn, F.ss, F.u, n2f, nxf, j, i);
+            const double r = F.f[(size_t)j * nxf + i] - apply_A(st, F.u, n2f, nxf, j, i);
             acc += wj * wi * r;
         }
     }
@@ -468,17 +542,17 @@ static int pcr_k(int total, int nt) {
     return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8;
 }
 
-template <int K, int NT>
+template <int K, int NT, class ST>
 static void relax_x1_launch(apic_ctx* ctx, int l, int color) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     const size_t lds = 4 * sizeof(double) * (size_t)(mn1 - 1);
     const int lines = (mn2 + 1 - color + 1) / 2;
     const int G = (int)ctx->grains.size();
-    hipLaunchKernelGGL((k_relax_x1<K, NT>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
+    hipLaunchKernelGGL((k_relax_x1<K, NT, ST>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
                        ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
 }
 
-template <int K, int LPB, int NT>
+template <int K, int LPB, int NT, class ST>
 static void relax_x2_launch(apic_ctx* ctx, int l, int color) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     const size_t lds = 4 * sizeof(double) * (size_t)LPB * (mn2 + 1);
@@ -486,35 +560,36 @@ static void relax_x2_launch(apic_ctx* ctx, int l, int color) {
     if (lines <= 0) return;
     const int blocks = (lines + LPB - 1) / LPB;
     const int G = (int)ctx->grains.size();
-    hipLaunchKernelGGL((k_relax_x2<K, LPB, NT>), dim3(round8(blocks), G), dim3(NT), lds, ctx->stream,
+    hipLaunchKernelGGL((k_relax_x2<K, LPB, NT, ST>), dim3(round8(blocks), G), dim3(NT), lds, ctx->stream,
                        ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
 }
 
-template <int NT>
+template <int NT, class ST>
 static void relax_x1_k(apic_ctx* ctx, int l, int color) {
     switch (pcr_k(ctx->lvl_max_n1[l] - 1, NT)) {
-        case 1: relax_x1_launch<1, NT>(ctx, l, color); break;
-        case 2: relax_x1_launch<2, NT>(ctx, l, color); break;
-        case 4: relax_x1_launch<4, NT>(ctx, l, color); break;
-        default: relax_x1_launch<8, NT>(ctx, l, color); break;
+        case 1: relax_x1_launch<1, NT, ST>(ctx, l, color); break;
+        case 2: relax_x1_launch<2, NT, ST>(ctx, l, color); break;
+        case 4: relax_x1_launch<4, NT, ST>(ctx, l, color); break;
+        default: relax_x1_launch<8, NT, ST>(ctx, l, color); break;
     }
 }
 
-template <int LPB, int NT>
+template <int LPB, int NT, class ST>
 static void relax_x2_k(apic_ctx* ctx, int l, int color) {
     switch (pcr_k(LPB * (ctx->lvl_max_n2[l] + 1), NT)) {
-        case 1: relax_x2_launch<1, LPB, NT>(ctx, l, color); break;
-        case 2: relax_x2_launch<2, LPB, NT>(ctx, l, color); break;
-        case 4: relax_x2_launch<4, LPB, NT>(ctx, l, color); break;
-        default: relax_x2_launch<8, LPB, NT>(ctx, l, color); break;
+        case 1: relax_x2_launch<1, LPB, NT, ST>(ctx, l, color); break;
+        case 2: relax_x2_launch<2, LPB, NT, ST>(ctx, l, color); break;
+        case 4: relax_x2_launch<4, LPB, NT, ST>(ctx, l, color); break;
+        default: relax_x2_launch<8, LPB, NT, ST>(ctx, l, color); break;
     }
 }
 
-static void relax(apic_ctx* ctx, int l) {
+template <class ST>
+static void relax_st(apic_ctx* ctx, int l) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     for (int color = 0; color < 2; ++color) {
-        if (mn1 - 1 > 512) relax_x1_k<512>(ctx, l, color);
-        else relax_x1_k<256>(ctx, l, color);
+        if (mn1 - 1 > 512) relax_x1_k<512, ST>(ctx, l, color);
+        else relax_x1_k<256, ST>(ctx, l, color);
     }
     const int Lx2 = mn2 + 1;
     const int lines = ctx->lvl_lines_x2[l];   // x2 lines of one colour, summed over grains
@@ -523,11 +598,17 @@ static void relax(apic_ctx* ctx, int l) {
                        lines / lpb < 2 * ctx->num_cus))
         lpb >>= 1;
     for (int color = 0; color < 2; ++color) {
-        if (lpb == 4) relax_x2_k<4, 256>(ctx, l, color);
-        else if (lpb == 2) relax_x2_k<2, 256>(ctx, l, color);
-        else if (Lx2 > 512) relax_x2_k<1, 512>(ctx, l, color);
-        else relax_x2_k<1, 256>(ctx, l, color);
+        if (lpb == 4) relax_x2_k<4, 256, ST>(ctx, l, color);
+        else if (lpb == 2) relax_x2_k<2, 256, ST>(ctx, l, color);
+        else if (Lx2 > 512) relax_x2_k<1, 512, ST>(ctx, l, color);
+        else relax_x2_k<1, 256, ST>(ctx, l, color);
     }
+}
+
+// the finest level's operator is evaluated at the nodes, the coarse ones are stored
+static void relax(apic_ctx* ctx, int l) {
+    if (l == 0) relax_st<FineStencil>(ctx, l);
+    else relax_st<StoredStencil>(ctx, l);
 }
 
 static void coarse_solve(apic_ctx* ctx, int l) {
@@ -575,9 +656,13 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
     for (int l = 0; l + 1 < nl; ++l) {
         relax(ctx, l);
         const int cn = ctx->lvl_max_nodes[l + 1];
-        hipLaunchKernelGGL(k_restrict_residual, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
-                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
-                           ctx->mgs);
+        if (l == 0)
+            hipLaunchKernelGGL(k_restrict_residual<FineStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
+                               dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
+        else
+            hipLaunchKernelGGL(k_restrict_residual<StoredStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
+                               dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G,
+                               ctx->mgdesc + (size_t)(l + 1) * G, ctx->mgs);
         coarse_solve(ctx, l + 1);
     }
     for (int l = nl - 2; l >= 0; --l) {
