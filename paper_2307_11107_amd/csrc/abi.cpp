@@ -263,6 +263,8 @@ void free_grain(Grain& g) {
         F(L.st);
         F(L.u);
         F(L.f);
+        F(L.uT);
+        F(L.fT);
     }
     g.mg.clear();
     g.ctr = nullptr;
@@ -477,7 +479,13 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
         TRY(alloc_t(ctx, &L.f, (size_t)L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.u, sizeof(double) * L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.f, sizeof(double) * L.nodes));
-        if (l == 0) continue;   // the finest operator is evaluated at the nodes
+        if (l == 0) {
+            // the finest operator is evaluated at the nodes; its x2 sweeps may
+            // use transposed copies of u and f
+            TRY(alloc_t(ctx, &L.uT, (size_t)L.nodes));
+            TRY(alloc_t(ctx, &L.fT, (size_t)L.nodes));
+            continue;
+        }
         TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
         stage.resize((size_t)ST_COUNT * L.nodes);
         for (int k = 0; k < ST_COUNT; ++k)
@@ -580,6 +588,11 @@ int build_tables(apic_ctx* ctx) {
         ctx->max_n1 = std::max(ctx->max_n1, g.gp.n1);
         ctx->max_n2 = std::max(ctx->max_n2, g.gp.n2);
     }
+    // the finest levels' u and f beyond half of the L2 caches (8 x 4 MB): x2
+    // sweeps on transposed copies
+    size_t fine_bytes = 0;
+    for (auto& g : ctx->grains) fine_bytes += 16 * (size_t)g.nodes;
+    ctx->x2_transposed = fine_bytes > ((size_t)16 << 20);
     TRY(alloc_t(ctx, &ctx->gdesc, (size_t)G));
     HIPCHK(ctx, hipMemcpy(ctx->gdesc, ctx->gdesc_h.data(), sizeof(GrainDesc) * G, hipMemcpyHostToDevice));
 
@@ -609,6 +622,8 @@ int build_tables(apic_ctx* ctx) {
             d.h2 = g.gp.h2 * (double)(1 << l);
             d.u = L.u;
             d.f = L.f;
+            d.uT = L.uT;
+            d.fT = L.fT;
             d.inv = d.coarsest ? g.coarse_inv : nullptr;
             ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
             if (!d.coarsest) {

@@ -120,6 +120,8 @@ struct MGDesc {
     const double* st;           // coarse levels: 9 stencil arrays [k * nodes + node]
     double* u;
     double* f;
+    double* uT;                 // finest level: u and f transposed (x2 fastest)
+    double* fT;
     const double* inv;          // dense inverse (coarsest only)
 };
 
@@ -145,6 +147,8 @@ struct MGLevel {
                                 // (coarse levels; the finest level's is evaluated at the nodes)
     double* u = nullptr;        // solution (level 0: phi) / correction
     double* f = nullptr;        // right-hand side
+    double* uT = nullptr;       // finest level: u, f transposed for the x2 sweeps
+    double* fT = nullptr;
 };
 
 struct Grain {
@@ -229,6 +233,7 @@ struct apic_ctx {
     int max_inj_bound = 0;                  // largest per-step injection of any task
     int max_ntiles = 0, max_sort_blocks = 0, max_segs = 0;
     int max_nodes = 0, max_n1 = 0, max_n2 = 0;
+    bool x2_transposed = false;             // finest-level x2 sweeps on transposed copies
     int pred_cycles = 0;                    // cycles of the previous in-step solve
     // schedule and graphs
     apic::Schedule sched;

@@ -310,6 +310,106 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     }
 }
 
+// ------------------------------------------------------------------ finest x2 lines
+// On the finest level the x2 sweeps run on transposed copies uT, fT (x2
+// fastest): an x2 line is then contiguous and its loads coalesce, instead of
+// every load of a wave touching 64 different rows.  u is transposed before
+// the x2 sweeps of a smoothing step and back after them; fT once per solve.
+// This pays when the finest levels of the ensemble do not fit in the L2
+// caches; small grids sweep the columns in place.
+constexpr int TR_TILE = 32;
+
+// which = 0: u -> uT, 1: uT -> u, 2: f -> fT
+template <int WHICH>
+__global__ void __launch_bounds__(256)
+k_transpose(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
+    __shared__ double t[TR_TILE][TR_TILE + 1];
+    const MGDesc& D = lv[blockIdx.y];
+    if (!level_active(D, ms)) return;
+    const int cols = D.n1 + 1, rows = D.n2 + 1;   // normal layout [row][col]
+    const int tiles_x = (cols + TR_TILE - 1) / TR_TILE;
+    const int tiles_y = (rows + TR_TILE - 1) / TR_TILE;
+    if ((int)blockIdx.x >= tiles_x * tiles_y) return;
+    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8 threads
+    if (WHICH == 1) {
+        // transposed [col][row] -> normal
+        for (int k = ly; k < TR_TILE; k += 8) {
+            const int i = tx * TR_TILE + k, j = ty * TR_TILE + lx;
+            if (i < cols && j < rows) t[k][lx] = D.uT[(size_t)i * rows + j];
+        }
+        __syncthreads();
+        for (int k = ly; k < TR_TILE; k += 8) {
+            const int j = ty * TR_TILE + k, i = tx * TR_TILE + lx;
+            if (i < cols && j < rows) D.u[(size_t)j * cols + i] = t[lx][k];
+        }
+    } else {
+        const double* src = WHICH == 0 ? D.u : D.f;
+        double* dst = WHICH == 0 ? D.uT : D.fT;
+        for (int k = ly; k < TR_TILE; k += 8) {
+            const int j = ty * TR_TILE + k, i = tx * TR_TILE + lx;
+            if (i < cols && j < rows) t[k][lx] = src[(size_t)j * cols + i];
+        }
+        __syncthreads();
+        for (int k = ly; k < TR_TILE; k += 8) {
+            const int i = tx * TR_TILE + k, j = ty * TR_TILE + lx;
+            if (i < cols && j < rows) dst[(size_t)i * rows + j] = t[lx][k];
+        }
+    }
+}
+
+// x2 lines i = 1 + color, 3 + color, ... of the finest level on uT / fT; the
+// axis rows' second-neighbour coupling is eliminated with the adjacent row.
+template <int K, int NT>
+__global__ void __launch_bounds__(NT)
+k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
+    extern __shared__ double lds[];
+    __shared__ double axis_nn, axis_ss;
+    const MGDesc& D = lv[blockIdx.y];
+    if (!level_active(D, ms)) return;
+    const int n1 = D.n1, n2 = D.n2;
+    const int i = 1 + color + 2 * xcd_line();
+    if (i > n1 - 1) return;
+    const int L = n2 + 1;
+    double* a = lds;
+    double* b = a + L;
+    double* c = b + L;
+    double* d = c + L;
+    const FineStencil st(D);
+    double* __restrict__ ut = D.uT;
+    const double* __restrict__ ft = D.fT;
+    const size_t base = (size_t)i * L;
+    for (int j = threadIdx.x; j < L; j += NT) {
+        const size_t o = base + j;
+        const Coef k = st.at(j, i, 0);
+        double rhs = ft[o] - k.W * ut[o - L] - k.E * ut[o + L];
+        if (j > 0) rhs -= k.SW * ut[o - L - 1] + k.SE * ut[o + L - 1];
+        if (j < n2) rhs -= k.NW * ut[o - L + 1] + k.NE * ut[o + L + 1];
+        a[j] = j > 0 ? k.S : 0.0;
+        b[j] = k.C;
+        c[j] = j < n2 ? k.N : 0.0;
+        d[j] = rhs;
+        if (j == 0) axis_nn = k.nn;
+        if (j == n2) axis_ss = k.ss;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mm = axis_nn / c[1];
+        b[0] -= mm * a[1];
+        c[0] -= mm * b[1];
+        d[0] -= mm * d[1];
+    }
+    if (threadIdx.x == 64) {
+        const double mm = axis_ss / a[n2 - 1];
+        a[n2] -= mm * b[n2 - 1];
+        b[n2] -= mm * c[n2 - 1];
+        d[n2] -= mm * d[n2 - 1];
+    }
+    __syncthreads();
+    pcr_solve<K, NT>(a, b, c, d, L, L);
+    for (int j = threadIdx.x; j < L; j += NT) ut[base + j] = d[j] * rcp64(b[j]);
+}
+
 // Block sum of a per-thread value (fixed order), written by thread 0.
 __device__ inline double block_sum(double v) {
     __shared__ double red[MG_BLOCK / 64];
@@ -399,52 +499,47 @@ __device__ inline double sum_parts(const double* __restrict__ p, int nb) {
     return block_sum(v);
 }
 
-// Convergence check after the residual norm: a grain is done once
-// |D^-1 r| <= tol |D^-1 b| (b with the boundary coupling) or when its residual
-// is not finite; count_cycle marks the check that ends a V-cycle; with_b also
-// takes |D^-1 b|^2 from its partial sums (start of a solve).  One workgroup.
+// Per grain (blockIdx.x), the partial norms of the grain summed in a fixed
+// order: ms.r2 (and, at the start of a solve, ms.b2).
 __global__ void __launch_bounds__(MG_BLOCK)
-k_mg_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int ngrains, int nb,
-           const double* __restrict__ part_r, const double* __restrict__ part_b, double tol2,
-           int count_cycle, MGBatch* __restrict__ mb) {
-    __shared__ int s_pending, s_nan, s_max;
+k_mg_sum(MGState* __restrict__ ms, int nb, const double* __restrict__ part_r, const double* __restrict__ part_b) {
+    const int g = blockIdx.x;
+    if (ms[g].done) return;
+    const double r2 = sum_parts(part_r + (size_t)g * nb, nb);
+    double b2 = 0.0;
+    if (part_b) b2 = sum_parts(part_b + (size_t)g * nb, nb);
     if (threadIdx.x == 0) {
-        s_pending = 0;
-        s_nan = mb->nan;
-        s_max = 0;
+        ms[g].r2 = r2;
+        if (part_b) ms[g].b2 = b2;
     }
-    __syncthreads();
+}
+
+// Convergence check after the residual norms: a grain is done once
+// |D^-1 r| <= tol |D^-1 b| (b with the boundary coupling) or when its residual
+// is not finite; count_cycle marks the check that ends a V-cycle.  One thread.
+__global__ void k_mg_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int ngrains, double tol2,
+                           int count_cycle, MGBatch* __restrict__ mb) {
+    if (threadIdx.x != 0) return;
+    int pending = 0, nan = mb->nan, maxc = 0;
     for (int g = 0; g < ngrains; ++g) {
         MGState& m = ms[g];
-        const int was_done = m.done;
-        double r2 = 0.0, b2 = 0.0;
-        if (!was_done) {
-            r2 = sum_parts(part_r + (size_t)g * nb, nb);
-            if (part_b) b2 = sum_parts(part_b + (size_t)g * nb, nb);
-        }
-        if (threadIdx.x == 0) {
-            if (!was_done) {
-                if (part_b) m.b2 = b2;
-                m.r2 = r2;
-                m.last_r2 = r2;
-                if (count_cycle) m.cycles += 1;
-                if (!(r2 == r2) || !(m.b2 == m.b2)) {
-                    s_nan = 1;
-                    m.done = 1;
-                } else if (r2 <= tol2 * (m.b2 + gd[g].bnd2)) {
-                    m.done = 1;
-                }
+        if (!m.done) {
+            const double r2 = m.r2;
+            m.last_r2 = r2;
+            if (count_cycle) m.cycles += 1;
+            if (!(r2 == r2) || !(m.b2 == m.b2)) {
+                nan = 1;
+                m.done = 1;
+            } else if (r2 <= tol2 * (m.b2 + gd[g].bnd2)) {
+                m.done = 1;
             }
-            s_pending += m.done ? 0 : 1;
-            s_max = max(s_max, m.cycles);
         }
-        __syncthreads();
+        pending += m.done ? 0 : 1;
+        maxc = max(maxc, m.cycles);
     }
-    if (threadIdx.x == 0) {
-        mb->pending = s_pending;
-        mb->nan = s_nan;
-        mb->max_cycles = s_max;
-    }
+    mb->pending = pending;
+    mb->nan = nan;
+    mb->max_cycles = maxc;
 }
 
 // Coarse right-hand side fc = P^T (f - A u) / 4 on the coarse unknowns, the
@@ -605,10 +700,53 @@ static void relax_st(apic_ctx* ctx, int l) {
     }
 }
 
-// the finest level's operator is evaluated at the nodes, the coarse ones are stored
+template <int WHICH>
+static void transpose(apic_ctx* ctx) {
+    const int G = (int)ctx->grains.size();
+    const int tiles = ((ctx->max_n1 + TR_TILE) / TR_TILE) * ((ctx->max_n2 + TR_TILE) / TR_TILE);
+    hipLaunchKernelGGL(k_transpose<WHICH>, dim3(tiles, G), dim3(256), 0, ctx->stream, ctx->mgdesc, ctx->mgs);
+}
+
+template <int K, int NT>
+static void relax_x2t_launch(apic_ctx* ctx, int color) {
+    const int G = (int)ctx->grains.size();
+    const int lines = (ctx->lvl_max_n1[0] - 1 - color + 1) / 2;
+    const size_t lds = 4 * sizeof(double) * (size_t)(ctx->lvl_max_n2[0] + 1);
+    hipLaunchKernelGGL((k_relax_x2t<K, NT>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream, ctx->mgdesc,
+                       ctx->mgs, color);
+}
+
+template <int NT>
+static void relax_x2t_k(apic_ctx* ctx, int color) {
+    switch (pcr_k(ctx->lvl_max_n2[0] + 1, NT)) {
+        case 1: relax_x2t_launch<1, NT>(ctx, color); break;
+        case 2: relax_x2t_launch<2, NT>(ctx, color); break;
+        case 4: relax_x2t_launch<4, NT>(ctx, color); break;
+        default: relax_x2t_launch<8, NT>(ctx, color); break;
+    }
+}
+
+// The finest level's operator is evaluated at the nodes (its x2 sweeps on the
+// transposed copies), the coarse ones are stored.
 static void relax(apic_ctx* ctx, int l) {
-    if (l == 0) relax_st<FineStencil>(ctx, l);
-    else relax_st<StoredStencil>(ctx, l);
+    if (l > 0) {
+        relax_st<StoredStencil>(ctx, l);
+        return;
+    }
+    if (!ctx->x2_transposed) {
+        relax_st<FineStencil>(ctx, 0);
+        return;
+    }
+    for (int color = 0; color < 2; ++color) {
+        if (ctx->lvl_max_n1[0] - 1 > 512) relax_x1_k<512, FineStencil>(ctx, 0, color);
+        else relax_x1_k<256, FineStencil>(ctx, 0, color);
+    }
+    transpose<0>(ctx);
+    for (int color = 0; color < 2; ++color) {
+        if (ctx->lvl_max_n2[0] + 1 > 512) relax_x2t_k<512>(ctx, color);
+        else relax_x2t_k<256>(ctx, color);
+    }
+    transpose<1>(ctx);
 }
 
 static void coarse_solve(apic_ctx* ctx, int l) {
@@ -630,8 +768,9 @@ static void residual_norm(apic_ctx* ctx) {
 static void check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
     const int G = (int)ctx->grains.size();
     const int nb = norm_blocks(ctx);
-    hipLaunchKernelGGL(k_mg_check, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, ctx->gdesc, G, nb,
-                       ctx->norm_part, with_b ? ctx->norm_part + (size_t)G * nb : nullptr, tol * tol,
+    hipLaunchKernelGGL(k_mg_sum, dim3(G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, nb, ctx->norm_part,
+                       with_b ? ctx->norm_part + (size_t)G * nb : nullptr);
+    hipLaunchKernelGGL(k_mg_check, dim3(1), dim3(64), 0, ctx->stream, ctx->mgs, ctx->gdesc, G, tol * tol,
                        count_cycle, ctx->mgb);
 }
 
@@ -645,6 +784,7 @@ hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain) {
                        ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
     residual_norm(ctx);
     check(ctx, tol, 0, true);
+    if (ctx->x2_transposed) transpose<2>(ctx);
     return hipGetLastError();
 }
 
