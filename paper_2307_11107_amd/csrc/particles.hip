@@ -785,22 +785,27 @@ __device__ inline bool key_cell(const GrainParams& gp, const PlainKey& k, int& i
     return true;
 }
 
-__device__ inline void load_rest(const PBuf& b, int64_t p, const SplitKey& k, SplitState& q) {
-    q.c = k.c;
-    if (k.c < 0) return;
+// the state besides the key; loaded whenever the slot exists, so the loads
+// need not wait for the key
+__device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, SplitState& q) {
+    if (p >= n) return;
     q.f1 = static_cast<const float*>(b.pos1)[p];
     q.f2 = static_cast<const float*>(b.pos2)[p];
     q.vR = static_cast<const float*>(b.vR)[p];
     q.vZ = static_cast<const float*>(b.vZ)[p];
     q.vT = static_cast<const float*>(b.vT)[p];
 }
-__device__ inline void load_rest(const PBuf& b, int64_t p, const PlainKey& k, PlainState& q) {
-    q.x1 = k.x1;
-    q.x2 = k.x2;
-    if (k.x1 > 0.0) return;
+__device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainState& q) {
+    if (p >= n) return;
     q.vR = static_cast<const double*>(b.vR)[p];
     q.vZ = static_cast<const double*>(b.vZ)[p];
     q.vT = static_cast<const double*>(b.vT)[p];
+}
+
+__device__ inline void set_key(SplitState& q, const SplitKey& k) { q.c = k.c; }
+__device__ inline void set_key(PlainState& q, const PlainKey& k) {
+    q.x1 = k.x1;
+    q.x2 = k.x2;
 }
 
 template <typename K, int PB>
@@ -855,27 +860,27 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
             if constexpr (SPLIT) K = split_consts(v.gp, v.sp);
         }
         const int64_t base = (c - v.first_chunk) * CHUNK + threadIdx.x;
-        Key key[PB + PUSH_AHEAD];
+        Key key[PB];
 #pragma unroll
         for (int k = 0; k < PB; ++k) load_key(v.b, base + k * BLOCK, v.n, key[k]);
-#pragma unroll
-        for (int k = PB; k < PB + PUSH_AHEAD; ++k) load_key(v.b, 0, 0, key[k]);
-        Window w;
-        w.on = false;
-        if (v.dep) w = keys_window(v.gp, reinterpret_cast<const Key(&)[PB]>(key), red);
+        // the first particles' states load while the window is reduced
         S ahead[PUSH_AHEAD + 1];
 #pragma unroll
-        for (int a = 0; a < PUSH_AHEAD; ++a) load_rest(v.b, base + a * BLOCK, key[a], ahead[a]);
+        for (int a = 0; a < PUSH_AHEAD; ++a) load_fields(v.b, base + a * BLOCK, v.n, ahead[a]);
+        Window w;
+        w.on = false;
+        if (v.dep) w = keys_window(v.gp, key, red);
 #pragma unroll 1
         for (int k = 0; k < PB; ++k) {
             const int64_t p = base + k * BLOCK;
             // the state PUSH_AHEAD particles ahead starts loading before this one is advanced
-            load_rest(v.b, p + PUSH_AHEAD * BLOCK, key[PUSH_AHEAD], ahead[PUSH_AHEAD]);
-            const S cur = ahead[0];
+            load_fields(v.b, p + PUSH_AHEAD * BLOCK, v.n, ahead[PUSH_AHEAD]);
+            S cur = ahead[0];
+            set_key(cur, key[0]);
 #pragma unroll
             for (int a = 0; a < PUSH_AHEAD; ++a) ahead[a] = ahead[a + 1];
 #pragma unroll
-            for (int a = 0; a < PB + PUSH_AHEAD - 1; ++a) key[a] = key[a + 1];
+            for (int a = 0; a < PB - 1; ++a) key[a] = key[a + 1];
             int ia, ic;
             T f, g;
             int r;
@@ -892,9 +897,10 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
             if (w.on) deposit_one(v.gp, w, win, v.dep, ia, ic, f, g);
         }
         if (w.on) {
+            // the next chunk's window reduction synchronises before anything
+            // is deposited again, which also covers the clearing of this window
             __syncthreads();
             flush_window(v.gp, w, win, v.dep);
-            __syncthreads();
         }
     }
     if (v.ctr) flush_counts(v.ctr, v.s, n_live, n_abs, n_esc);
