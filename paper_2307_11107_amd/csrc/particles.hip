@@ -648,8 +648,11 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w, doub
 // A particle then needs two integer LDS atomics (bottom and top edge of its
 // cell) instead of four float ones, and the window sums do not depend on the
 // order of the additions.  With C copies a copy receives at most CHUNK / C
-// particles, which sets the fraction bits: 20 + log2(C) (2^-20 .. 2^-24).
-__device__ inline int fx_bits(int C) { return 20 + (31 - __clz(C)); }
+// particles, each adding at most 1: the fraction bits 31 - log2(CHUNK / C)
+// keep every 32-bit sum below 2^31 (2^-20 .. 2^-24 for CHUNK = 2048).
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+constexpr int SPLIT_CHUNK_LOG2 = ilog2(PushTraits<true>::PB * BLOCK);
+__device__ inline int fx_bits(int C) { return 31 - SPLIT_CHUNK_LOG2 + (31 - __clz(C)); }
 
 __device__ inline void deposit_one(const GrainParams& gp, const Window& w,
                                    unsigned long long* __restrict__ win, float* __restrict__ dep,
