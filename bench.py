@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-ensemble", action="store_true")
-    ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--ensemble-steps", type=int, default=16)
     ap.add_argument("--ensemble-warmup", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -75,3 +75,27 @@ __host__ __device__ inline int cell_i1(int32_t c) { return c & 0xFFFF; }
 __host__ __device__ inline int cell_i2(int32_t c) { return (int)((uint32_t)c >> 16); }
 
 }  // namespace apic
+
+namespace apic {
+
+// ---------------------------------------------------------------- global memory
+// Pointers taken from descriptor tables in device memory are generic to the
+// compiler, which then emits flat instructions (slower, and counted against
+// the LDS wait counter too).  gbl() states that a pointer is global memory.
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T* p) { return (gptr<T>)p; }
+
+__device__ __forceinline__ void gadd(float* p, float v) {
+    __hip_atomic_fetch_add(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(double* p, double v) {
+    __hip_atomic_fetch_add(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace apic

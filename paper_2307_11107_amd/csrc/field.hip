@@ -39,8 +39,8 @@ k_clear_deposits(const GrainDesc* __restrict__ gd, int word_bytes) {
     const int i = blockIdx.x * FB + threadIdx.x;
     if (i >= G.nodes) return;
     for (int s = 0; s < G.ns; ++s) {
-        if (word_bytes == 4) static_cast<float*>(const_cast<void*>(G.dep[s]))[i] = 0.f;
-        else static_cast<double*>(const_cast<void*>(G.dep[s]))[i] = 0.0;
+        if (word_bytes == 4) gbl(static_cast<float*>(const_cast<void*>(G.dep[s])))[i] = 0.f;
+        else gbl(static_cast<double*>(const_cast<void*>(G.dep[s])))[i] = 0.0;
     }
 }
 
@@ -58,12 +58,12 @@ k_rho_rhs(const GrainDesc* __restrict__ gd) {
     const GrainDesc& G = gd[blockIdx.y];
     const int i = blockIdx.x * FB + threadIdx.x;
     if (i >= G.nodes) return;
-    double q = G.cw[0] * (double)static_cast<const D*>(G.dep[0])[i];
-    if (G.ns > 1) q += G.cw[1] * (double)static_cast<const D*>(G.dep[1])[i];
-    const double rho = q / G.vol[i];
-    G.rho[i] = rho;
+    double q = G.cw[0] * (double)gbl(static_cast<const D*>(G.dep[0]))[i];
+    if (G.ns > 1) q += G.cw[1] * (double)gbl(static_cast<const D*>(G.dep[1]))[i];
+    const double rho = q / gbl(G.vol)[i];
+    gbl(G.rho)[i] = rho;
     const int i1 = i % G.nx;
-    G.f[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * rho;
+    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * rho;
 }
 
 hipError_t launch_rho_rhs(apic_ctx* ctx) {
@@ -81,7 +81,7 @@ k_rhs(const GrainDesc* __restrict__ gd, int grain) {
     const int i = blockIdx.x * FB + threadIdx.x;
     if (i >= G.nodes) return;
     const int i1 = i % G.nx;
-    G.f[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * G.rho[i];
+    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * gbl(G.rho)[i];
 }
 
 hipError_t launch_rhs_from_rho(apic_ctx* ctx, int grain) {
@@ -96,8 +96,8 @@ k_set_boundary(const GrainDesc* __restrict__ gd) {
     const GrainDesc& G = gd[blockIdx.y];
     const int j = blockIdx.x * FB + threadIdx.x;
     if (j > G.n2) return;
-    G.u[j * G.nx] = G.phi_grain;
-    G.u[j * G.nx + G.n1] = G.phi_out;
+    gbl(G.u)[j * G.nx] = G.phi_grain;
+    gbl(G.u)[j * G.nx + G.n1] = G.phi_out;
 }
 
 hipError_t launch_set_boundary(apic_ctx* ctx) {
@@ -116,7 +116,7 @@ k_gradient(const GrainDesc* __restrict__ gd) {
     const int n1 = G.n1, n2 = G.n2, nx = G.nx;
     const int i2 = idx / nx, i1 = idx - i2 * nx;
     const double ih1 = G.inv_h1, ih2 = G.inv_h2;
-    const double* row = G.u + (size_t)i2 * nx;
+    const gptr<const double> row = gbl(static_cast<const double*>(G.u) + (size_t)i2 * nx);
     double d1, d2;
     if (i1 == 0) d1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * ih1;
     else if (i1 == n1) d1 = (3.0 * row[n1] - 4.0 * row[n1 - 1] + row[n1 - 2]) * 0.5 * ih1;
@@ -124,10 +124,10 @@ k_gradient(const GrainDesc* __restrict__ gd) {
     if (i2 == 0) d2 = (-3.0 * row[i1] + 4.0 * row[i1 + nx] - row[i1 + 2 * nx]) * 0.5 * ih2;
     else if (i2 == n2) d2 = (3.0 * row[i1] - 4.0 * row[i1 - nx] + row[i1 - 2 * nx]) * 0.5 * ih2;
     else d2 = (row[i1 + nx] - row[i1 - nx]) * 0.5 * ih2;
-    V v;
-    v.x = d1;
-    v.y = d2;
-    static_cast<V*>(G.grad)[idx] = v;
+    using E = decltype(V().x);
+    const gptr<E> g = gbl(static_cast<E*>(G.grad));
+    g[2 * (size_t)idx] = (E)d1;
+    g[2 * (size_t)idx + 1] = (E)d2;
 }
 
 hipError_t launch_gradient(apic_ctx* ctx) {
@@ -154,7 +154,7 @@ k_grain_force(const GrainDesc* __restrict__ gd) {
         const double s = sqrt(fmax(1.0 - x2 * x2, 0.0));
         const Metric<double> m = metric_at(r, x2, s, alpha);
         const double gn = sqrt(m.x1R * m.x1R + m.x1Z * m.x1Z);
-        const double* row = G.u + (size_t)j * nx;
+        const gptr<const double> row = gbl(static_cast<const double*>(G.u) + (size_t)j * nx);
         const double p1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * G.inv_h1;
         const double En = -gn * p1;
         const double t = alpha / (r + 2.0 * alpha * x2);
@@ -168,7 +168,7 @@ k_grain_force(const GrainDesc* __restrict__ gd) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) G.ctr->F_el_sum += red[0] * h2;
+    if (threadIdx.x == 0) gbl(&G.ctr->F_el_sum)[0] += red[0] * h2;
 }
 
 hipError_t launch_grain_force(apic_ctx* ctx) {

@@ -15,6 +15,7 @@
 // V-cycle ends with the row-scaled residual norm and a convergence check on
 // the device, so cycles can be replayed from a graph without host reads.
 #include "apic_internal.h"
+#include "device_common.h"
 
 namespace apic {
 
@@ -34,7 +35,7 @@ __device__ inline double rcp64(double x) {
 // couples only inside its system; a[first] = c[last] = 0.  Each thread owns up
 // to K equations.  On return d[e] / b[e] is the solution.
 template <int K, int NT>
-__device__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int total) {
+__device__ __forceinline__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int total) {
     int jj[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) jj[k] = (threadIdx.x + k * NT) % L;
@@ -88,9 +89,9 @@ struct Coef {
 
 // Coarse levels: the Galerkin stencil arrays.
 struct StoredStencil {
-    const double* st;
+    gptr<const double> st;
     int nodes, n2;
-    __device__ explicit StoredStencil(const MGDesc& D) : st(D.st), nodes(D.nodes), n2(D.n2) {}
+    __device__ explicit StoredStencil(const MGDesc& D) : st(gbl(D.st)), nodes(D.nodes), n2(D.n2) {}
     __device__ Coef at(int, int, size_t o) const {
         const size_t n = (size_t)nodes;
         Coef c;
@@ -164,7 +165,7 @@ struct FineStencil {
 
 // (A u) at an unknown node (j, i) of a level.
 template <class ST>
-__device__ inline double apply_A(const ST& st, const double* __restrict__ u, int n2, int nx, int j, int i) {
+__device__ inline double apply_A(const ST& st, gptr<const double> u, int n2, int nx, int j, int i) {
     const size_t o = (size_t)j * nx + i;
     const Coef k = st.at(j, i, o);
     double au = k.C * u[o] + k.W * u[o - 1] + k.E * u[o + 1];
@@ -204,8 +205,8 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     double* d = c + L;
     const int nx = n1 + 1;
     const ST st(D);
-    double* __restrict__ u = D.u;
-    const double* __restrict__ f = D.f;
+    const gptr<double> u = gbl(D.u);
+    const gptr<const double> f = gbl(static_cast<const double*>(D.f));
     for (int k = threadIdx.x; k < L; k += NT) {
         const int i = k + 1;
         const size_t o = (size_t)j * nx + i;
@@ -251,8 +252,8 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     double* d = c + total;
     const int nx = n1 + 1;
     const ST st(D);
-    double* __restrict__ u = D.u;
-    const double* __restrict__ f = D.f;
+    const gptr<double> u = gbl(D.u);
+    const gptr<const double> f = gbl(static_cast<const double*>(D.f));
     for (int q = threadIdx.x; q < total; q += NT) {
         const int m = q % LPB, j = q / LPB;
         const int i = i0 + 2 * m;
@@ -336,16 +337,16 @@ k_transpose(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
         // transposed [col][row] -> normal
         for (int k = ly; k < TR_TILE; k += 8) {
             const int i = tx * TR_TILE + k, j = ty * TR_TILE + lx;
-            if (i < cols && j < rows) t[k][lx] = D.uT[(size_t)i * rows + j];
+            if (i < cols && j < rows) t[k][lx] = gbl(D.uT)[(size_t)i * rows + j];
         }
         __syncthreads();
         for (int k = ly; k < TR_TILE; k += 8) {
             const int j = ty * TR_TILE + k, i = tx * TR_TILE + lx;
-            if (i < cols && j < rows) D.u[(size_t)j * cols + i] = t[lx][k];
+            if (i < cols && j < rows) gbl(D.u)[(size_t)j * cols + i] = t[lx][k];
         }
     } else {
-        const double* src = WHICH == 0 ? D.u : D.f;
-        double* dst = WHICH == 0 ? D.uT : D.fT;
+        const gptr<const double> src = gbl(static_cast<const double*>(WHICH == 0 ? D.u : D.f));
+        const gptr<double> dst = gbl(WHICH == 0 ? D.uT : D.fT);
         for (int k = ly; k < TR_TILE; k += 8) {
             const int j = ty * TR_TILE + k, i = tx * TR_TILE + lx;
             if (i < cols && j < rows) t[k][lx] = src[(size_t)j * cols + i];
@@ -376,8 +377,8 @@ k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int c
     double* c = b + L;
     double* d = c + L;
     const FineStencil st(D);
-    double* __restrict__ ut = D.uT;
-    const double* __restrict__ ft = D.fT;
+    const gptr<double> ut = gbl(D.uT);
+    const gptr<const double> ft = gbl(static_cast<const double*>(D.fT));
     const size_t base = (size_t)i * L;
     for (int j = threadIdx.x; j < L; j += NT) {
         const size_t o = base + j;
@@ -444,12 +445,13 @@ k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, d
         if (i > 0 && i < n1) {
             const FineStencil st(D);
             const Coef k = st.at(j, i, idx);
-            double au = k.C * D.u[idx] + k.W * D.u[idx - 1] + k.E * D.u[idx + 1];
-            if (j > 0) au += k.S * D.u[idx - nx] + k.SW * D.u[idx - nx - 1] + k.SE * D.u[idx - nx + 1];
-            if (j < n2) au += k.N * D.u[idx + nx] + k.NW * D.u[idx + nx - 1] + k.NE * D.u[idx + nx + 1];
-            if (j == 0) au += k.nn * D.u[idx + 2 * nx];
-            if (j == n2) au += k.ss * D.u[idx - 2 * nx];
-            const double q = (D.f[idx] - au) / k.C;
+            const gptr<const double> u = gbl(static_cast<const double*>(D.u));
+            double au = k.C * u[idx] + k.W * u[idx - 1] + k.E * u[idx + 1];
+            if (j > 0) au += k.S * u[idx - nx] + k.SW * u[idx - nx - 1] + k.SE * u[idx - nx + 1];
+            if (j < n2) au += k.N * u[idx + nx] + k.NW * u[idx + nx - 1] + k.NE * u[idx + nx + 1];
+            if (j == 0) au += k.nn * u[idx + 2 * nx];
+            if (j == n2) au += k.ss * u[idx - 2 * nx];
+            const double q = (gbl(D.f)[idx] - au) / k.C;
             rr = q * q;
         }
     }
@@ -473,7 +475,7 @@ k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double
         const int i = idx % nx;
         if (i > 0 && i < D.n1) {
             const FineStencil st(D);
-            const double q = D.f[idx] / st.diag(idx / nx, i, idx);
+            const double q = gbl(D.f)[idx] / st.diag(idx / nx, i, idx);
             v = q * q;
         }
     }
@@ -557,10 +559,10 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
     const int n2f = F.n2, nxf = F.n1 + 1;
     const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
     if (idx >= C.nodes) return;
-    C.u[idx] = 0.0;
+    gbl(C.u)[idx] = 0.0;
     const int J = idx / nxc, I = idx - J * nxc;
     if (I == 0 || I == n1c) {
-        C.f[idx] = 0.0;
+        gbl(C.f)[idx] = 0.0;
         return;
     }
     const ST st(F);
@@ -572,11 +574,11 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
         for (int di = -1; di <= 1; ++di) {
             const int i = 2 * I + di;      // 1 <= i <= n1f - 1
             const double wi = di == 0 ? 1.0 : 0.5;
-            const double r = F.f[(size_t)j * nxf + i] - apply_A(st, F.u, n2f, nxf, j, i);
+            const double r = gbl(F.f)[(size_t)j * nxf + i] - apply_A(st, gbl(static_cast<const double*>(F.u)), n2f, nxf, j, i);
             acc += wj * wi * r;
         }
     }
-    C.f[idx] = 0.25 * acc;
+    gbl(C.f)[idx] = 0.25 * acc;
 }
 
 // fine u += P uc (bilinear) on the fine unknowns
@@ -594,10 +596,10 @@ k_prolong_add(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse
     const int J0 = j >> 1, I0 = i >> 1;
     const int J1 = (j & 1) ? J0 + 1 : J0;
     const int I1 = (i & 1) ? I0 + 1 : I0;
-    const double* uc = C.u;
+    const gptr<const double> uc = gbl(static_cast<const double*>(C.u));
     const double v = 0.25 * (uc[(size_t)J0 * nxc + I0] + uc[(size_t)J0 * nxc + I1] +
                              uc[(size_t)J1 * nxc + I0] + uc[(size_t)J1 * nxc + I1]);
-    F.u[idx] += v;
+    gbl(F.u)[idx] += v;
 }
 
 // Dense solve on a grain's coarsest level: u = A^-1 rhs with rhs = f on the
@@ -614,15 +616,15 @@ k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
     if (row >= m) return;
     const int ri = row % nx;
     if (ri == 0 || ri == D.n1) return;
-    const double* a = D.inv + (size_t)row * m;
+    const gptr<const double> a = gbl(D.inv + (size_t)row * m);
     double acc = 0.0;
     for (int k = lane; k < m; k += 64) {
         const int i = k % nx;
-        acc += a[k] * ((i == 0 || i == D.n1) ? D.u[k] : D.f[k]);
+        acc += a[k] * ((i == 0 || i == D.n1) ? gbl(D.u)[k] : gbl(D.f)[k]);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) D.u[row] = acc;
+    if (lane == 0) gbl(D.u)[row] = acc;
 }
 
 // ------------------------------------------------------------------ launches

@@ -34,7 +34,7 @@ namespace apic {
 constexpr int BLOCK = 256;
 constexpr double FP64_DEAD = 1.0;   // x1 of a dead FP64 slot (valid x1 < 0)
 
-__device__ inline void atomic_add_f64(double* p, double v) { atomicAdd(p, v); }
+__device__ inline void atomic_add_f64(double* p, double v) { gadd(p, v); }
 
 // Block-wide sum of a per-thread u32 followed by one atomic per block.
 __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
@@ -47,7 +47,7 @@ __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
-        if (t) atomicAdd(dst, (unsigned long long)t);
+        if (t) gadd(dst, (unsigned long long)t);
     }
     __syncthreads();
 }
@@ -95,7 +95,7 @@ __device__ __attribute__((noinline)) void tally_impact(double alpha_d, int n_bin
     atomic_add_f64(&tally[2 * stride + o], sp.m * sp.w * (double)vZ);
     atomic_add_f64(&tally[3 * stride + o], sp.m * sp.w * (double)Ri * vTi);
     atomic_add_f64(&tally[4 * stride + o], sp.w * (0.5 * sp.m * v2 + sp.e_bind));
-    atomicAdd(&tally_count[o], 1ull);
+    gadd(&tally_count[o], 1ull);
 }
 
 // Closest approach of the chord to the origin; returns t in (0,1) if the point
@@ -158,12 +158,12 @@ struct SplitState {
 
 __device__ inline SplitState load_split(const PBuf& b, int64_t p) {
     SplitState q;
-    q.c = static_cast<const int32_t*>(b.pos0)[p];
-    q.f1 = static_cast<const float*>(b.pos1)[p];
-    q.f2 = static_cast<const float*>(b.pos2)[p];
-    q.vR = static_cast<const float*>(b.vR)[p];
-    q.vZ = static_cast<const float*>(b.vZ)[p];
-    q.vT = static_cast<const float*>(b.vT)[p];
+    q.c = gbl(static_cast<const int32_t*>(b.pos0))[p];
+    q.f1 = gbl(static_cast<const float*>(b.pos1))[p];
+    q.f2 = gbl(static_cast<const float*>(b.pos2))[p];
+    q.vR = gbl(static_cast<const float*>(b.vR))[p];
+    q.vZ = gbl(static_cast<const float*>(b.vZ))[p];
+    q.vT = gbl(static_cast<const float*>(b.vT))[p];
     return q;
 }
 
@@ -179,12 +179,12 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
                                      int& i2n, float& f1n, float& f2n) {
     const int32_t c = q.c;
     if (c < 0) return -1;
-    int32_t* __restrict__ cell = static_cast<int32_t*>(b.pos0);
-    float* __restrict__ f1a = static_cast<float*>(b.pos1);
-    float* __restrict__ f2a = static_cast<float*>(b.pos2);
-    float* __restrict__ vRa = static_cast<float*>(b.vR);
-    float* __restrict__ vZa = static_cast<float*>(b.vZ);
-    float* __restrict__ vTa = static_cast<float*>(b.vT);
+    const gptr<int32_t> cell = gbl(static_cast<int32_t*>(b.pos0));
+    const gptr<float> f1a = gbl(static_cast<float*>(b.pos1));
+    const gptr<float> f2a = gbl(static_cast<float*>(b.pos2));
+    const gptr<float> vRa = gbl(static_cast<float*>(b.vR));
+    const gptr<float> vZa = gbl(static_cast<float*>(b.vZ));
+    const gptr<float> vTa = gbl(static_cast<float*>(b.vT));
     const int n1 = K.n1, n2 = K.n2, nx = K.nx;
     const float alpha = K.alpha, h1 = K.h1, h2 = K.h2, qmh = K.qmh, step = K.step;
     const int i1 = cell_i1(c), i2 = cell_i2(c);
@@ -193,8 +193,11 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
 
     // gather (bilinear in the logical coordinates)
     const int idx = i2 * nx + i1;
-    const float2 g00 = grad[idx], g10 = grad[idx + 1];
-    const float2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
+    // float2 nodes read as 64-bit words (the vector type cannot be copied out
+    // of an explicitly global reference)
+    const gptr<const unsigned long long> gr = gbl(reinterpret_cast<const unsigned long long*>(grad));
+    const float2 g00 = __builtin_bit_cast(float2, gr[idx]), g10 = __builtin_bit_cast(float2, gr[idx + 1]);
+    const float2 g01 = __builtin_bit_cast(float2, gr[idx + nx]), g11 = __builtin_bit_cast(float2, gr[idx + nx + 1]);
     const float e1 = 1.f - f1, e2 = 1.f - f2;
     const float w00 = e1 * e2, w10 = f1 * e2, w01 = e1 * f2, w11 = f1 * f2;
     const float p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
@@ -327,10 +330,10 @@ __device__ inline void deposit64(const GrainParams& gp, double* dep, double x1, 
     double f1, f2;
     locate64(gp, x1, x2, i1, i2, f1, f2);
     const int o = i2 * gp.nx + i1;
-    atomicAdd(&dep[o], (1 - f1) * (1 - f2));
-    atomicAdd(&dep[o + 1], f1 * (1 - f2));
-    atomicAdd(&dep[o + gp.nx], (1 - f1) * f2);
-    atomicAdd(&dep[o + gp.nx + 1], f1 * f2);
+    gadd(&dep[o], (1 - f1) * (1 - f2));
+    gadd(&dep[o + 1], f1 * (1 - f2));
+    gadd(&dep[o + gp.nx], (1 - f1) * f2);
+    gadd(&dep[o + gp.nx + 1], f1 * f2);
 }
 
 // Drift, boundary test, tally: shared by the FP64 push and by injection.
@@ -368,11 +371,11 @@ struct PlainState {
 
 __device__ inline PlainState load_plain(const PBuf& b, int64_t p) {
     PlainState q;
-    q.x1 = static_cast<const double*>(b.pos1)[p];
-    q.x2 = static_cast<const double*>(b.pos2)[p];
-    q.vR = static_cast<const double*>(b.vR)[p];
-    q.vZ = static_cast<const double*>(b.vZ)[p];
-    q.vT = static_cast<const double*>(b.vT)[p];
+    q.x1 = gbl(static_cast<const double*>(b.pos1))[p];
+    q.x2 = gbl(static_cast<const double*>(b.pos2))[p];
+    q.vR = gbl(static_cast<const double*>(b.vR))[p];
+    q.vZ = gbl(static_cast<const double*>(b.vZ))[p];
+    q.vT = gbl(static_cast<const double*>(b.vT))[p];
     return q;
 }
 
@@ -386,11 +389,11 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
                                      int& i2n, double& f1n, double& f2n) {
     const double x1 = q.x1;
     if (x1 > 0.0) return -1;
-    double* __restrict__ x1a = static_cast<double*>(b.pos1);
-    double* __restrict__ x2a = static_cast<double*>(b.pos2);
-    double* __restrict__ vRa = static_cast<double*>(b.vR);
-    double* __restrict__ vZa = static_cast<double*>(b.vZ);
-    double* __restrict__ vTa = static_cast<double*>(b.vT);
+    const gptr<double> x1a = gbl(static_cast<double*>(b.pos1));
+    const gptr<double> x2a = gbl(static_cast<double*>(b.pos2));
+    const gptr<double> vRa = gbl(static_cast<double*>(b.vR));
+    const gptr<double> vZa = gbl(static_cast<double*>(b.vZ));
+    const gptr<double> vTa = gbl(static_cast<double*>(b.vT));
     const int nx = gp.nx;
     const double alpha = gp.alpha;
     const double x2 = q.x2;
@@ -399,8 +402,11 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
     double f1, f2;
     locate64(gp, x1, x2, i1, i2, f1, f2);
     const int idx = i2 * nx + i1;
-    const double2 g00 = grad[idx], g10 = grad[idx + 1];
-    const double2 g01 = grad[idx + nx], g11 = grad[idx + nx + 1];
+    const gptr<const double> gr = gbl(reinterpret_cast<const double*>(grad));
+    const double2 g00 = make_double2(gr[2 * idx], gr[2 * idx + 1]);
+    const double2 g10 = make_double2(gr[2 * idx + 2], gr[2 * idx + 3]);
+    const double2 g01 = make_double2(gr[2 * (idx + nx)], gr[2 * (idx + nx) + 1]);
+    const double2 g11 = make_double2(gr[2 * (idx + nx) + 2], gr[2 * (idx + nx) + 3]);
     const double w00 = (1 - f1) * (1 - f2), w10 = f1 * (1 - f2);
     const double w01 = (1 - f1) * f2, w11 = f1 * f2;
     const double p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
@@ -619,10 +625,10 @@ __device__ inline void deposit_one(const GrainParams& gp, const Window& w, doubl
     } else {
         const int nx = gp.nx;
         const int o = i2 * nx + i1;
-        atomicAdd(&dep[o], w00);
-        atomicAdd(&dep[o + 1], w10);
-        atomicAdd(&dep[o + nx], w01);
-        atomicAdd(&dep[o + nx + 1], w11);
+        gadd(&dep[o], w00);
+        gadd(&dep[o + 1], w10);
+        gadd(&dep[o + nx], w01);
+        gadd(&dep[o + nx + 1], w11);
     }
 }
 
@@ -638,7 +644,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w, doub
         }
         if (val != 0.0) {
             const int row = q / w.W;
-            atomicAdd(&dep[(w.wj0 + row) * nx + w.wi0 + (q - row * w.W)], val);
+            gadd(&dep[(w.wj0 + row) * nx + w.wi0 + (q - row * w.W)], val);
         }
     }
 }
@@ -673,10 +679,10 @@ __device__ inline void deposit_one(const GrainParams& gp, const Window& w,
     } else {
         const int nx = gp.nx;
         const int o = i2 * nx + i1;
-        atomicAdd(&dep[o], w00);
-        atomicAdd(&dep[o + 1], w10);
-        atomicAdd(&dep[o + nx], w01);
-        atomicAdd(&dep[o + nx + 1], w11);
+        gadd(&dep[o], w00);
+        gadd(&dep[o + 1], w10);
+        gadd(&dep[o + nx], w01);
+        gadd(&dep[o + nx + 1], w11);
     }
 }
 
@@ -690,7 +696,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
         for (int c = 0; c < C; ++c) sum += win[q * C + ((c + q) & (C - 1))] & 0xFFFFFFFFull;
         if (col > 0)
             for (int c = 0; c < C; ++c) sum += win[(q - 1) * C + ((c + q) & (C - 1))] >> 32;
-        if (sum) atomicAdd(&dep[(w.wj0 + row) * nx + w.wi0 + col], (float)((double)sum * isc));
+        if (sum) gadd(&dep[(w.wj0 + row) * nx + w.wi0 + col], (float)((double)sum * isc));
     }
     __syncthreads();
     for (int q = threadIdx.x; q < nodes_w * C; q += BLOCK) win[q] = 0ull;
@@ -763,12 +769,12 @@ struct SplitKey { int32_t c; };
 struct PlainKey { double x1, x2; };
 
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, SplitKey& k) {
-    k.c = p < n ? static_cast<const int32_t*>(b.pos0)[p] : DEAD;
+    k.c = p < n ? gbl(static_cast<const int32_t*>(b.pos0))[p] : DEAD;
 }
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, PlainKey& k) {
     if (p < n) {
-        k.x1 = static_cast<const double*>(b.pos1)[p];
-        k.x2 = static_cast<const double*>(b.pos2)[p];
+        k.x1 = gbl(static_cast<const double*>(b.pos1))[p];
+        k.x2 = gbl(static_cast<const double*>(b.pos2))[p];
     } else {
         k.x1 = FP64_DEAD;
         k.x2 = 0.0;
@@ -792,17 +798,17 @@ __device__ inline bool key_cell(const GrainParams& gp, const PlainKey& k, int& i
 // need not wait for the key
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, SplitState& q) {
     if (p >= n) return;
-    q.f1 = static_cast<const float*>(b.pos1)[p];
-    q.f2 = static_cast<const float*>(b.pos2)[p];
-    q.vR = static_cast<const float*>(b.vR)[p];
-    q.vZ = static_cast<const float*>(b.vZ)[p];
-    q.vT = static_cast<const float*>(b.vT)[p];
+    q.f1 = gbl(static_cast<const float*>(b.pos1))[p];
+    q.f2 = gbl(static_cast<const float*>(b.pos2))[p];
+    q.vR = gbl(static_cast<const float*>(b.vR))[p];
+    q.vZ = gbl(static_cast<const float*>(b.vZ))[p];
+    q.vT = gbl(static_cast<const float*>(b.vT))[p];
 }
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainState& q) {
     if (p >= n) return;
-    q.vR = static_cast<const double*>(b.vR)[p];
-    q.vZ = static_cast<const double*>(b.vZ)[p];
-    q.vT = static_cast<const double*>(b.vT)[p];
+    q.vR = gbl(static_cast<const double*>(b.vR))[p];
+    q.vZ = gbl(static_cast<const double*>(b.vZ))[p];
+    q.vT = gbl(static_cast<const double*>(b.vT))[p];
 }
 
 __device__ inline void set_key(SplitState& q, const SplitKey& k) { q.c = k.c; }
@@ -995,24 +1001,24 @@ __device__ inline void store_particle(const GrainParams& gp, bool split, const P
         float ff1 = (float)f1, ff2 = (float)f2;
         if (ff1 >= 1.f) ff1 = 0.99999994f;
         if (ff2 >= 1.f) ff2 = 0.99999994f;
-        static_cast<int32_t*>(b.pos0)[p] = pack_cell(i1, i2);
-        static_cast<float*>(b.pos1)[p] = ff1;
-        static_cast<float*>(b.pos2)[p] = ff2;
-        static_cast<float*>(b.vR)[p] = (float)vR;
-        static_cast<float*>(b.vZ)[p] = (float)vZ;
-        static_cast<float*>(b.vT)[p] = (float)vT;
+        gbl(static_cast<int32_t*>(b.pos0))[p] = pack_cell(i1, i2);
+        gbl(static_cast<float*>(b.pos1))[p] = ff1;
+        gbl(static_cast<float*>(b.pos2))[p] = ff2;
+        gbl(static_cast<float*>(b.vR))[p] = (float)vR;
+        gbl(static_cast<float*>(b.vZ))[p] = (float)vZ;
+        gbl(static_cast<float*>(b.vT))[p] = (float)vT;
     } else {
-        static_cast<double*>(b.pos1)[p] = x1;
-        static_cast<double*>(b.pos2)[p] = x2;
-        static_cast<double*>(b.vR)[p] = vR;
-        static_cast<double*>(b.vZ)[p] = vZ;
-        static_cast<double*>(b.vT)[p] = vT;
+        gbl(static_cast<double*>(b.pos1))[p] = x1;
+        gbl(static_cast<double*>(b.pos2))[p] = x2;
+        gbl(static_cast<double*>(b.vR))[p] = vR;
+        gbl(static_cast<double*>(b.vZ))[p] = vZ;
+        gbl(static_cast<double*>(b.vT))[p] = vT;
     }
 }
 
 __device__ inline void store_dead(bool split, const PBuf& b, int64_t p) {
-    if (split) static_cast<int32_t*>(b.pos0)[p] = DEAD;
-    else static_cast<double*>(b.pos1)[p] = FP64_DEAD;
+    if (split) gbl(static_cast<int32_t*>(b.pos0))[p] = DEAD;
+    else gbl(static_cast<double*>(b.pos1))[p] = FP64_DEAD;
 }
 
 // ----------------------------------------------------------------- volume load
@@ -1047,7 +1053,7 @@ k_load(GrainParams gp, SpeciesParams sp, int s, int64_t n, bool split, PBuf b) {
         const double vZ = sp.sigma * g0 * sin(tp * unit_open(v.y));
         const double vT = sp.sigma * g1 * cos(tp * unit_open(v.w));
         store_particle(gp, split, b, k, x1, x2, vR, vZ, vT);
-        b.id[k] = (uint32_t)k;
+        gbl(b.id)[k] = (uint32_t)k;
     }
 }
 
@@ -1060,12 +1066,12 @@ k_set(GrainParams gp, int64_t n, bool split, PBuf b, const double* __restrict__ 
          k += (int64_t)gridDim.x * blockDim.x) {
         const double a = x1[k], c = x2[k];
         if (!(a > -1.0 && a < gp.x1_out && c >= -1.0 && c <= 1.0)) {
-            atomicOr(bad, 1);
+            __hip_atomic_fetch_or(gbl(bad), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             store_dead(split, b, k);
         } else {
             store_particle(gp, split, b, k, a, c, vR[k], vZ[k], vT[k]);
         }
-        b.id[k] = (uint32_t)k;
+        gbl(b.id)[k] = (uint32_t)k;
     }
 }
 
@@ -1156,7 +1162,7 @@ k_inject(const PushTask* __restrict__ tasks, bool split, int deposit) {
         double x1n, x2n, vRn, vTn;
         const int st = drift_and_bound64(gp, sp, s, ns, r * sn, r * x2, vR, vZ, vT,
                                          gp.step * frac, x1n, x2n, vRn, vTn, tally, tally_count);
-        b.id[slot] = id0 + (uint32_t)k;
+        gbl(b.id)[slot] = id0 + (uint32_t)k;
         if (st != 0) {
             store_dead(split, b, slot);
             if (st == 1) ++n_abs; else ++n_esc;
@@ -1165,15 +1171,15 @@ k_inject(const PushTask* __restrict__ tasks, bool split, int deposit) {
         store_particle(gp, split, b, slot, x1n, x2n, vRn, vZ, vTn);
         if (dep) {
             if (split) {
-                const int32_t c = static_cast<int32_t*>(b.pos0)[slot];
-                const float f1 = static_cast<float*>(b.pos1)[slot];
-                const float f2 = static_cast<float*>(b.pos2)[slot];
+                const int32_t c = gbl(static_cast<int32_t*>(b.pos0))[slot];
+                const float f1 = gbl(static_cast<float*>(b.pos1))[slot];
+                const float f2 = gbl(static_cast<float*>(b.pos2))[slot];
                 float* d = static_cast<float*>(dep);
                 const int o = cell_i2(c) * gp.nx + cell_i1(c);
-                atomicAdd(&d[o], (1.f - f1) * (1.f - f2));
-                atomicAdd(&d[o + 1], f1 * (1.f - f2));
-                atomicAdd(&d[o + gp.nx], (1.f - f1) * f2);
-                atomicAdd(&d[o + gp.nx + 1], f1 * f2);
+                gadd(&d[o], (1.f - f1) * (1.f - f2));
+                gadd(&d[o + 1], f1 * (1.f - f2));
+                gadd(&d[o + gp.nx], (1.f - f1) * f2);
+                gadd(&d[o + gp.nx + 1], f1 * f2);
             } else {
                 deposit64(gp, static_cast<double*>(dep), x1n, x2n);
             }
@@ -1193,29 +1199,29 @@ k_readback(GrainParams gp, int s, bool split, PBuf b, const DevCounters* __restr
          p += (int64_t)gridDim.x * blockDim.x) {
         double x1, x2, vR, vZ, vT;
         if (split) {
-            const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
+            const int32_t c = gbl(static_cast<const int32_t*>(b.pos0))[p];
             if (c < 0) continue;
-            x1 = -1.0 + ((double)cell_i1(c) + (double)static_cast<const float*>(b.pos1)[p]) * gp.h1;
-            const double u = ((double)cell_i2(c) + (double)static_cast<const float*>(b.pos2)[p]) * gp.h2;
+            x1 = -1.0 + ((double)cell_i1(c) + (double)gbl(static_cast<const float*>(b.pos1))[p]) * gp.h1;
+            const double u = ((double)cell_i2(c) + (double)gbl(static_cast<const float*>(b.pos2))[p]) * gp.h2;
             x2 = -1.0 + u;
-            vR = static_cast<const float*>(b.vR)[p];
-            vZ = static_cast<const float*>(b.vZ)[p];
-            vT = static_cast<const float*>(b.vT)[p];
+            vR = gbl(static_cast<const float*>(b.vR))[p];
+            vZ = gbl(static_cast<const float*>(b.vZ))[p];
+            vT = gbl(static_cast<const float*>(b.vT))[p];
         } else {
-            x1 = static_cast<const double*>(b.pos1)[p];
+            x1 = gbl(static_cast<const double*>(b.pos1))[p];
             if (x1 > 0.0) continue;
-            x2 = static_cast<const double*>(b.pos2)[p];
-            vR = static_cast<const double*>(b.vR)[p];
-            vZ = static_cast<const double*>(b.vZ)[p];
-            vT = static_cast<const double*>(b.vT)[p];
+            x2 = gbl(static_cast<const double*>(b.pos2))[p];
+            vR = gbl(static_cast<const double*>(b.vR))[p];
+            vZ = gbl(static_cast<const double*>(b.vZ))[p];
+            vT = gbl(static_cast<const double*>(b.vT))[p];
         }
-        const unsigned long long o = atomicAdd(cursor, 1ull);
+        const unsigned long long o = __hip_atomic_fetch_add(gbl(cursor), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x1o[o] = x1;
         x2o[o] = x2;
         vRo[o] = vR;
         vZo[o] = vZ;
         vTo[o] = vT;
-        ido[o] = (int64_t)b.id[p];
+        ido[o] = (int64_t)gbl(b.id)[p];
     }
 }
 
@@ -1238,15 +1244,15 @@ int scan_seg_len() { return SCAN_SEG; }
 __device__ inline int tile_key(const GrainParams& gp, bool split, const PBuf& b, int64_t p) {
     int i1, i2;
     if (split) {
-        const int32_t c = static_cast<const int32_t*>(b.pos0)[p];
+        const int32_t c = gbl(static_cast<const int32_t*>(b.pos0))[p];
         if (c < 0) return -1;
         i1 = cell_i1(c);
         i2 = cell_i2(c);
     } else {
-        const double x1 = static_cast<const double*>(b.pos1)[p];
+        const double x1 = gbl(static_cast<const double*>(b.pos1))[p];
         if (x1 > 0.0) return -1;
         double f1, f2;
-        locate64(gp, x1, static_cast<const double*>(b.pos2)[p], i1, i2, f1, f2);
+        locate64(gp, x1, gbl(static_cast<const double*>(b.pos2))[p], i1, i2, f1, f2);
     }
     return (i2 >> gp.tile_log2) * gp.ntx + (i1 >> gp.tile_log2);
 }
@@ -1292,7 +1298,7 @@ k_tile_hist(const PushTask* __restrict__ tasks, bool split) {
         if (is_head && key >= 0) atomicAdd(&lh[key], len);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nt; t += BLOCK) T.hist[(size_t)t * SB + blockIdx.x] = lh[t];
+    for (int t = threadIdx.x; t < nt; t += BLOCK) gbl(T.hist)[(size_t)t * SB + blockIdx.x] = lh[t];
 }
 
 // Exclusive scan of every task's histogram (length ntiles * sort_blocks) in
@@ -1327,11 +1333,11 @@ k_scan_reduce(const PushTask* __restrict__ tasks) {
     if (lo >= len) return;
     const int64_t hi = min<int64_t>(lo + SCAN_SEG, len);
     int v = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) v += T.hist[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLOCK) v += gbl(T.hist)[i];
     __shared__ int tmp[BLOCK / 64];
     int total;
     (void)block_scan_excl(v, tmp, total);
-    if (threadIdx.x == 0) T.seg[blockIdx.x] = total;
+    if (threadIdx.x == 0) gbl(T.seg)[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(1024)
@@ -1343,14 +1349,14 @@ k_scan_segs(const PushTask* __restrict__ tasks) {
     int carry = 0;
     for (int k0 = 0; k0 < nseg; k0 += 1024) {
         const int k = k0 + threadIdx.x;
-        const int v = k < nseg ? T.seg[k] : 0;
+        const int v = k < nseg ? gbl(T.seg)[k] : 0;
         int total;
         const int ex = block_scan_excl(v, tmp, total);
-        if (k < nseg) T.seg[k] = carry + ex;
+        if (k < nseg) gbl(T.seg)[k] = carry + ex;
         carry += total;
     }
     if (threadIdx.x == 0) {
-        T.hist_off[len] = carry;
+        gbl(T.hist_off)[len] = carry;
         T.ctr->n_sorted[T.s] = carry;
     }
 }
@@ -1367,15 +1373,15 @@ k_scan_apply(const PushTask* __restrict__ tasks) {
     int sum = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = (i0 + k < len) ? T.hist[i0 + k] : 0;
+        v[k] = (i0 + k < len) ? gbl(T.hist)[i0 + k] : 0;
         sum += v[k];
     }
     __shared__ int tmp[BLOCK / 64];
     int total;
-    int run = T.seg[blockIdx.x] + block_scan_excl(sum, tmp, total);
+    int run = gbl(T.seg)[blockIdx.x] + block_scan_excl(sum, tmp, total);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (i0 + k < len) T.hist_off[i0 + k] = run;
+        if (i0 + k < len) gbl(T.hist_off)[i0 + k] = run;
         run += v[k];
     }
 }
@@ -1390,38 +1396,38 @@ struct Moved {
 
 __device__ inline void load_moved(bool split, const PBuf& b, int64_t p, Moved& m) {
     if (split) {
-        m.w[0] = static_cast<const uint32_t*>(b.pos0)[p];
-        m.w[1] = static_cast<const uint32_t*>(b.pos1)[p];
-        m.w[2] = static_cast<const uint32_t*>(b.pos2)[p];
-        m.w[3] = static_cast<const uint32_t*>(b.vR)[p];
-        m.w[4] = static_cast<const uint32_t*>(b.vZ)[p];
-        m.vT = static_cast<const uint32_t*>(b.vT)[p];
+        m.w[0] = gbl(static_cast<const uint32_t*>(b.pos0))[p];
+        m.w[1] = gbl(static_cast<const uint32_t*>(b.pos1))[p];
+        m.w[2] = gbl(static_cast<const uint32_t*>(b.pos2))[p];
+        m.w[3] = gbl(static_cast<const uint32_t*>(b.vR))[p];
+        m.w[4] = gbl(static_cast<const uint32_t*>(b.vZ))[p];
+        m.vT = gbl(static_cast<const uint32_t*>(b.vT))[p];
     } else {
-        m.d[0] = static_cast<const uint64_t*>(b.pos1)[p];
-        m.d[1] = static_cast<const uint64_t*>(b.pos2)[p];
-        m.d[2] = static_cast<const uint64_t*>(b.vR)[p];
-        m.d[3] = static_cast<const uint64_t*>(b.vZ)[p];
-        m.d[4] = static_cast<const uint64_t*>(b.vT)[p];
+        m.d[0] = gbl(static_cast<const uint64_t*>(b.pos1))[p];
+        m.d[1] = gbl(static_cast<const uint64_t*>(b.pos2))[p];
+        m.d[2] = gbl(static_cast<const uint64_t*>(b.vR))[p];
+        m.d[3] = gbl(static_cast<const uint64_t*>(b.vZ))[p];
+        m.d[4] = gbl(static_cast<const uint64_t*>(b.vT))[p];
     }
-    m.id = b.id[p];
+    m.id = gbl(b.id)[p];
 }
 
 __device__ inline void store_moved(bool split, const PBuf& b, int64_t o, const Moved& m) {
     if (split) {
-        static_cast<uint32_t*>(b.pos0)[o] = m.w[0];
-        static_cast<uint32_t*>(b.pos1)[o] = m.w[1];
-        static_cast<uint32_t*>(b.pos2)[o] = m.w[2];
-        static_cast<uint32_t*>(b.vR)[o] = m.w[3];
-        static_cast<uint32_t*>(b.vZ)[o] = m.w[4];
-        static_cast<uint32_t*>(b.vT)[o] = m.vT;
+        gbl(static_cast<uint32_t*>(b.pos0))[o] = m.w[0];
+        gbl(static_cast<uint32_t*>(b.pos1))[o] = m.w[1];
+        gbl(static_cast<uint32_t*>(b.pos2))[o] = m.w[2];
+        gbl(static_cast<uint32_t*>(b.vR))[o] = m.w[3];
+        gbl(static_cast<uint32_t*>(b.vZ))[o] = m.w[4];
+        gbl(static_cast<uint32_t*>(b.vT))[o] = m.vT;
     } else {
-        static_cast<uint64_t*>(b.pos1)[o] = m.d[0];
-        static_cast<uint64_t*>(b.pos2)[o] = m.d[1];
-        static_cast<uint64_t*>(b.vR)[o] = m.d[2];
-        static_cast<uint64_t*>(b.vZ)[o] = m.d[3];
-        static_cast<uint64_t*>(b.vT)[o] = m.d[4];
+        gbl(static_cast<uint64_t*>(b.pos1))[o] = m.d[0];
+        gbl(static_cast<uint64_t*>(b.pos2))[o] = m.d[1];
+        gbl(static_cast<uint64_t*>(b.vR))[o] = m.d[2];
+        gbl(static_cast<uint64_t*>(b.vZ))[o] = m.d[3];
+        gbl(static_cast<uint64_t*>(b.vT))[o] = m.d[4];
     }
-    b.id[o] = m.id;
+    gbl(b.id)[o] = m.id;
 }
 
 // Scatter: SCATTER_BATCHES batches of BLOCK particles per iteration, all their
@@ -1437,7 +1443,7 @@ k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
     if ((int)blockIdx.x >= SB) return;
     const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
-    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = T.hist_off[(size_t)t * SB + blockIdx.x];
+    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = gbl(T.hist_off)[(size_t)t * SB + blockIdx.x];
     __syncthreads();
     const int which = T.ctr->cur[T.s];
     const PBuf src = T.buf[which];
@@ -1485,8 +1491,8 @@ k_count_live(int s, bool split, PBuf b, const DevCounters* __restrict__ ctr,
     uint32_t live = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
-        if (split) live += static_cast<const int32_t*>(b.pos0)[p] >= 0;
-        else live += !(static_cast<const double*>(b.pos1)[p] > 0.0);
+        if (split) live += gbl(static_cast<const int32_t*>(b.pos0))[p] >= 0;
+        else live += !(gbl(static_cast<const double*>(b.pos1))[p] > 0.0);
     }
     block_count_add(live, out);
 }
