@@ -289,6 +289,10 @@ void free_ctx(apic_ctx* ctx) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
 }
 
@@ -689,6 +693,28 @@ int sort_every(const apic_ctx* ctx) {
 // One step of every grain: push (gather, kick, drift, boundaries, deposit),
 // injection, charge density, FP64 solve, nodal gradient, grain force; a sort
 // every sort_every steps.
+// The sort of a step runs on the side stream, overlapped with the field solve
+// of the same step (the solve needs only the deposit, the sort only the
+// particles); the main stream waits for it at the end of the step.
+int sort_all_async(apic_ctx* ctx) {
+    HIPCHK(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    hipStream_t main = ctx->stream;
+    ctx->stream = ctx->side;
+    int rc;
+    {
+        Timer t(ctx, 2);
+        rc = sort_all(ctx);
+    }
+    ctx->stream = main;
+    TRY(rc);
+    HIPCHK(ctx, hipEventRecord(ctx->ev_join, ctx->side));
+    return APIC_OK;
+}
+
+// One step of every grain: push (gather, kick, drift, boundaries, deposit),
+// injection, charge density, FP64 solve, nodal gradient, grain force; a sort
+// every sort_every steps.
 int do_step(apic_ctx* ctx) {
     const bool frozen = frozen_mode(ctx);
     bool stale = false;
@@ -704,6 +730,9 @@ int do_step(apic_ctx* ctx) {
         Timer t(ctx, 1);
         TRY(run_phase(ctx, G_INJ, [&] { (void)launch_inject(ctx, !frozen); }));
     }
+    const uint64_t step = ctx->grains[0].step_index + 1;
+    const bool sort_now = step % (uint64_t)sort_every(ctx) == 0;
+    if (sort_now) TRY(sort_all_async(ctx));
     {
         Timer t(ctx, 3);
         if (!frozen) {
@@ -716,12 +745,8 @@ int do_step(apic_ctx* ctx) {
             (void)launch_grain_force(ctx);
         }));
     }
+    if (sort_now) HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
     for (auto& g : ctx->grains) g.step_index++;
-    const uint64_t step = ctx->grains[0].step_index;
-    if (step % (uint64_t)sort_every(ctx) == 0) {
-        Timer t(ctx, 2);
-        TRY(sort_all(ctx));
-    }
     if (ctx->profiling) ++ctx->timed_steps;
     return APIC_OK;
 }
@@ -892,6 +917,16 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
             return APIC_EDEVICE;
         }
         ctx->own_stream = true;
+    }
+    // side stream (default priority) for the sort overlapped with the solve
+    e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        g_init_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+        free_ctx(ctx);
+        delete ctx;
+        return APIC_EDEVICE;
     }
     ctx->grains.resize(n_grains);
     // host tables of all grains in parallel, then the device side in order

@@ -211,6 +211,8 @@ struct apic_ctx {
     apic_opts opts;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;             // sort overlapped with the field solve
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool graphs = true;                     // capture repeated launch sequences
     int device = 0;
     int num_cus = 256;
