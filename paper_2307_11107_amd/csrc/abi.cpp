@@ -165,8 +165,9 @@ int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bo
     if (in_step) {
         TRY(run_phase(ctx, G_PRE, [&] {
             (void)launch_rho_rhs(ctx);
+            (void)mg_extrapolate(ctx);
             (void)launch_set_boundary(ctx);
-            (void)mg_begin(ctx, tol, -1);
+            (void)mg_begin(ctx, tol, -1, true);
         }));
         const int pred = std::min(ctx->pred_cycles, max_cycles);
         for (; launched < pred; ++launched)
@@ -180,7 +181,7 @@ int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bo
         ctx->pred_cycles = b.max_cycles;
     } else {
         HIPCHK(ctx, launch_set_boundary(ctx));
-        HIPCHK(ctx, mg_begin(ctx, tol, only));
+        HIPCHK(ctx, mg_begin(ctx, tol, only, false));
         TRY(read_batch(ctx, b));
         double prev = HUGE_VAL;
         while (b.pending > 0 && launched < max_cycles) {
@@ -265,6 +266,7 @@ void free_grain(Grain& g) {
         F(L.f);
         F(L.uT);
         F(L.fT);
+        F(L.uprev);
     }
     g.mg.clear();
     g.ctr = nullptr;
@@ -330,9 +332,22 @@ void set_tiles(GrainParams& gp, int t) {
 struct HostSetup {
     std::vector<Stencil> levels;
     std::vector<double> inv;
+    int max_dense = 600;        // largest level solved by the dense inverse
+    int threads = 1;            // host threads for the inverse
     int rc = APIC_OK;
     std::string err;
 };
+
+// The coarsest level of a grain's hierarchy is solved by a dense inverse (one
+// matrix-vector product per V-cycle, bandwidth-bound); every level above it
+// costs ten latency-bound launches per cycle.  So the coarsest level is made as
+// large as the ensemble's inverses allow: about 192 MB of them in total, at
+// most 4400 nodes (65 x 65) and at least 600 per grain.
+constexpr int DENSE_MAX_NODES = 4400;
+int dense_limit(int n_grains) {
+    const double per = 192.0 * (1 << 20) / (8.0 * n_grains);
+    return std::max(600, std::min(DENSE_MAX_NODES, (int)std::sqrt(per)));
+}
 
 void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     g.cfg = c;
@@ -404,11 +419,15 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     }
 
     // multigrid hierarchy: coarsen by two while both cell counts are even and
-    // at least 8, and stop at the first level with at most 600 nodes (solved
-    // by a dense inverse)
+    // at least 8, and stop at the first level small enough for the dense
+    // inverse.  The finest level itself is solved densely only when it is very
+    // small: one product with a large inverse is less accurate than V-cycles
+    // iterated on the FP64 residual, while on a correction level it is exact
+    // enough.
     hs.levels.resize(1);
     fine_stencil(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
-    while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > 600 && hs.levels.back().n1 % 2 == 0 &&
+    while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > (hs.levels.size() == 1 ? 600 : hs.max_dense) &&
+           hs.levels.back().n1 % 2 == 0 &&
            hs.levels.back().n2 % 2 == 0 && std::min(hs.levels.back().n1, hs.levels.back().n2) / 2 >= 4) {
         Stencil cs;
         galerkin_coarse(hs.levels.back(), cs);
@@ -416,14 +435,14 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     }
     const Stencil& last = hs.levels.back();
     const int m = (last.n1 + 1) * (last.n2 + 1);
-    if (m > 4096) {
+    if (m > DENSE_MAX_NODES) {
         hs.rc = APIC_ERANGE;
         hs.err = "grid does not coarsen far enough for multigrid";
         return;
     }
     std::vector<double> A;
     dense_matrix(last, A);
-    if (!invert(A, m, hs.inv)) {
+    if (!invert(A, m, hs.inv, hs.threads)) {
         hs.rc = APIC_EDEVICE;
         hs.err = "coarsest multigrid operator is singular";
         return;
@@ -488,6 +507,7 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             // use transposed copies of u and f
             TRY(alloc_t(ctx, &L.uT, (size_t)L.nodes));
             TRY(alloc_t(ctx, &L.fT, (size_t)L.nodes));
+            TRY(alloc_t(ctx, &L.uprev, (size_t)L.nodes));
             continue;
         }
         TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
@@ -628,6 +648,7 @@ int build_tables(apic_ctx* ctx) {
             d.f = L.f;
             d.uT = L.uT;
             d.fT = L.fT;
+            d.uprev = L.uprev;
             d.inv = d.coarsest ? g.coarse_inv : nullptr;
             ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
             if (!d.coarsest) {
@@ -932,7 +953,12 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
     // host tables of all grains in parallel, then the device side in order
     std::vector<HostSetup> hs(n_grains);
     {
-        const int nt = std::max(1, std::min<int>(n_grains, (int)std::thread::hardware_concurrency()));
+        const int hw = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+        const int nt = std::min(n_grains, hw);
+        for (auto& h : hs) {
+            h.max_dense = dense_limit(n_grains);
+            h.threads = std::max(1, hw / nt);
+        }
         std::vector<std::thread> pool;
         for (int w = 0; w < nt; ++w)
             pool.emplace_back([&, w] {

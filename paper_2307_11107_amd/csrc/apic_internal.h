@@ -122,6 +122,7 @@ struct MGDesc {
     double* f;
     double* uT;                 // finest level: u and f transposed (x2 fastest)
     double* fT;
+    double* uprev;              // finest level: the potential of the previous step
     const double* inv;          // dense inverse (coarsest only)
 };
 
@@ -132,6 +133,8 @@ struct MGState {
     double last_r2;             // r2 of the last check
     int done;                   // converged (or excluded from this solve)
     int cycles;                 // cycles run in this solve
+    int extrap;                 // uprev holds the previous in-step solution
+    int pad;
 };
 
 struct MGBatch {
@@ -149,6 +152,7 @@ struct MGLevel {
     double* f = nullptr;        // right-hand side
     double* uT = nullptr;       // finest level: u, f transposed for the x2 sweeps
     double* fT = nullptr;
+    double* uprev = nullptr;    // finest level: previous step's potential
 };
 
 struct Grain {
@@ -281,7 +285,8 @@ hipError_t launch_grain_force(apic_ctx* ctx);
 hipError_t launch_set_boundary(apic_ctx* ctx);
 
 // multigrid.hip
-hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain);
+hipError_t mg_extrapolate(apic_ctx* ctx);
+hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step);
 hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol);
 
 }  // namespace apic

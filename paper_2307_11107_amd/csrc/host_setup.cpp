@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <stdexcept>
+#include <thread>
 #include <vector>
 
 #include "host_setup.h"
@@ -270,35 +271,64 @@ void dense_matrix(const Stencil& s, std::vector<double>& A) {
         }
 }
 
-// Gauss-Jordan inversion with partial pivoting.
-bool invert(std::vector<double> A, int m, std::vector<double>& inv) {
-    inv.assign((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) inv[(size_t)i * m + i] = 1.0;
+// Inverse of a banded m x m matrix (row-major; zero outside |r - c| <= w, w
+// found from the entries): Gaussian elimination with partial pivoting inside
+// the band (the rows of U then reach at most 2w past the diagonal, the row
+// interchanges are applied as they occur, as in banded LINPACK), then one
+// solve per column of the identity, the columns split over `threads`.
+// Returns false on a zero pivot.
+bool invert(std::vector<double> A, int m, std::vector<double>& inv, int threads) {
+    int w = 0;
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c)
+            if (A[(size_t)r * m + c] != 0.0) w = std::max(w, std::abs(r - c));
+    std::vector<int> piv(m);
     for (int col = 0; col < m; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < m; ++r)
-            if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
-        if (A[(size_t)piv * m + col] == 0.0) return false;
-        if (piv != col)
-            for (int k = 0; k < m; ++k) {
-                std::swap(A[(size_t)piv * m + k], A[(size_t)col * m + k]);
-                std::swap(inv[(size_t)piv * m + k], inv[(size_t)col * m + k]);
-            }
+        const int rend = std::min(m, col + w + 1), cend = std::min(m, col + 2 * w + 1);
+        int p = col;
+        for (int r = col + 1; r < rend; ++r)
+            if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)p * m + col])) p = r;
+        if (A[(size_t)p * m + col] == 0.0) return false;
+        piv[col] = p;
+        if (p != col)
+            for (int k = col; k < cend; ++k) std::swap(A[(size_t)p * m + k], A[(size_t)col * m + k]);
         const double d = 1.0 / A[(size_t)col * m + col];
-        for (int k = 0; k < m; ++k) {
-            A[(size_t)col * m + k] *= d;
-            inv[(size_t)col * m + k] *= d;
-        }
-        for (int r = 0; r < m; ++r) {
-            if (r == col) continue;
-            const double f = A[(size_t)r * m + col];
-            if (f == 0.0) continue;
-            for (int k = 0; k < m; ++k) {
-                A[(size_t)r * m + k] -= f * A[(size_t)col * m + k];
-                inv[(size_t)r * m + k] -= f * inv[(size_t)col * m + k];
-            }
+        for (int r = col + 1; r < rend; ++r) {
+            double& l = A[(size_t)r * m + col];
+            if (l == 0.0) continue;
+            l *= d;
+            for (int k = col + 1; k < cend; ++k) A[(size_t)r * m + k] -= l * A[(size_t)col * m + k];
         }
     }
+    inv.assign((size_t)m * m, 0.0);
+    auto columns = [&](int first, int step) {
+        std::vector<double> b(m);
+        for (int k = first; k < m; k += step) {
+            std::fill(b.begin(), b.end(), 0.0);
+            b[k] = 1.0;
+            // forward: the interchanges and multipliers of the elimination
+            // (nothing happens before column k - w)
+            for (int col = std::max(0, k - w); col < m; ++col) {
+                if (piv[col] != col) std::swap(b[piv[col]], b[col]);
+                const double t = b[col];
+                if (t == 0.0) continue;
+                const int rend = std::min(m, col + w + 1);
+                for (int r = col + 1; r < rend; ++r) b[r] -= A[(size_t)r * m + col] * t;
+            }
+            for (int r = m - 1; r >= 0; --r) {
+                double v = b[r];
+                const int cend = std::min(m, r + 2 * w + 1);
+                for (int c = r + 1; c < cend; ++c) v -= A[(size_t)r * m + c] * b[c];
+                b[r] = v / A[(size_t)r * m + r];
+            }
+            for (int r = 0; r < m; ++r) inv[(size_t)r * m + k] = b[r];
+        }
+    };
+    threads = std::max(1, std::min(threads, m));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(columns, t, threads);
+    columns(0, threads);
+    for (auto& t : pool) t.join();
     return true;
 }
 

@@ -24,7 +24,7 @@ double grain_max_radius(double alpha);
 void fine_stencil(int n1, int n2, double x1_out, double alpha, Stencil& s);
 void galerkin_coarse(const Stencil& fine, Stencil& coarse);
 void dense_matrix(const Stencil& s, std::vector<double>& A);
-bool invert(std::vector<double> A, int m, std::vector<double>& inv);
+bool invert(std::vector<double> A, int m, std::vector<double>& inv, int threads);
 double boundary_coupling_norm2(const Stencil& s, double phi_grain, double phi_out);
 
 }  // namespace apic

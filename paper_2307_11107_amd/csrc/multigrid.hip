@@ -4,8 +4,9 @@
 // the same discrete system is solved by multigrid V-cycles: Galerkin coarse
 // operators (R A P, bilinear P, R = P^T / 4, built on the host), alternating
 // zebra line Gauss-Seidel smoothing (x1-lines, then x2-lines; each line is a
-// tridiagonal system solved in LDS by parallel cyclic reduction), and a dense
-// inverse on the coarsest grid (at most a few hundred nodes).  The operator's
+// tridiagonal system solved in LDS by parallel cyclic reduction, or, for the
+// many long lines of a large ensemble, by the partition method), and a dense
+// inverse on the coarsest grid (a few hundred to a few thousand nodes).  The operator's
 // anisotropy changes direction across the domain (the x1 coefficient falls like
 // r^-4), which is why both line directions are relaxed.
 //
@@ -79,6 +80,80 @@ __device__ __forceinline__ void pcr_solve(double* a, double* b, double* c, doubl
         }
         __syncthreads();
     }
+}
+
+// Tridiagonal systems held in LDS (a: sub, b: diagonal, c: super, d: rhs;
+// equations 0..total-1, systems concatenated with a[first] = c[last] = 0),
+// solved by the partition method.  Thread t takes the chunk of P consecutive
+// equations starting at t P into registers; a forward and a backward
+// elimination pass inside the chunk express each of its unknowns through the
+// chunk's first and last unknowns.  Those 2 NT unknowns satisfy a tridiagonal
+// system of their own (the chunk's first equation couples the previous
+// chunk's last unknown, its last equation the next chunk's first), solved by
+// cyclic reduction in LDS; every thread then recovers its chunk.  Without
+// pivoting, as the line systems of the discrete operator are diagonally
+// dominant.  Needs P >= 2, NT P >= total and LDS arrays of max(total, 2 NT)
+// entries; on return d[e] holds the solution.
+template <int P, int NT>
+__device__ __forceinline__ void tri_solve(double* a, double* b, double* c, double* d, int total) {
+    static_assert(P >= 2, "a chunk needs a first and a last equation");
+    const int e0 = threadIdx.x * P;
+    double A[P], B[P], C[P], D[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int e = e0 + p;
+        const bool in = e < total;
+        A[p] = in ? a[e] : 0.0;
+        B[p] = in ? b[e] : 1.0;
+        C[p] = in ? c[e] : 0.0;
+        D[p] = in ? d[e] : 0.0;
+    }
+    __syncthreads();
+    // forward pass: equation p >= 1 becomes A[p] y_0 + y_p + C[p] y_{p+1} = D[p]
+    double pa = -1.0, pc = 0.0, pd = 0.0;
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        const double r = rcp64(B[p] - A[p] * pc);
+        pa = -A[p] * pa * r;
+        pd = (D[p] - A[p] * pd) * r;
+        pc = C[p] * r;
+        A[p] = pa;
+        C[p] = pc;
+        D[p] = pd;
+    }
+    const double la = A[P - 1], lc = C[P - 1], ld = D[P - 1];
+    // backward pass: equation P-2 .. 1 becomes A[p] y_0 + y_p + C[p] y_{P-1} = D[p]
+    double xa = 0.0, xc = -1.0, xd = 0.0;
+#pragma unroll
+    for (int p = P - 2; p >= 1; --p) {
+        const double cp = C[p];
+        A[p] -= cp * xa;
+        D[p] -= cp * xd;
+        C[p] = -cp * xc;
+        xa = A[p];
+        xc = C[p];
+        xd = D[p];
+    }
+    const int r0 = 2 * threadIdx.x;
+    a[r0] = A[0];
+    b[r0] = B[0] - C[0] * xa;
+    c[r0] = -C[0] * xc;
+    d[r0] = D[0] - C[0] * xd;
+    a[r0 + 1] = la;
+    b[r0 + 1] = 1.0;
+    c[r0 + 1] = lc;
+    d[r0 + 1] = ld;
+    __syncthreads();
+    pcr_solve<2, NT>(a, b, c, d, 2 * NT, 2 * NT);
+    const double y0 = d[r0] * rcp64(b[r0]);
+    const double yl = d[r0 + 1] * rcp64(b[r0 + 1]);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int e = e0 + p;
+        if (e < total) d[e] = p == 0 ? y0 : p == P - 1 ? yl : D[p] - A[p] * y0 - C[p] * yl;
+    }
+    __syncthreads();
 }
 
 // Coefficients of the 9-point operator at one unknown node (nn / ss: the
@@ -361,7 +436,7 @@ k_transpose(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
 
 // x2 lines i = 1 + color, 3 + color, ... of the finest level on uT / fT; the
 // axis rows' second-neighbour coupling is eliminated with the adjacent row.
-template <int K, int NT>
+template <int P, int NT>
 __global__ void __launch_bounds__(NT)
 k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
     extern __shared__ double lds[];
@@ -372,10 +447,11 @@ k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int c
     const int i = 1 + color + 2 * xcd_line();
     if (i > n1 - 1) return;
     const int L = n2 + 1;
+    const int cap = L > 2 * NT ? L : 2 * NT;
     double* a = lds;
-    double* b = a + L;
-    double* c = b + L;
-    double* d = c + L;
+    double* b = a + cap;
+    double* c = b + cap;
+    double* d = c + cap;
     const FineStencil st(D);
     const gptr<double> ut = gbl(D.uT);
     const gptr<const double> ft = gbl(static_cast<const double*>(D.fT));
@@ -399,16 +475,14 @@ k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int c
         b[0] -= mm * a[1];
         c[0] -= mm * b[1];
         d[0] -= mm * d[1];
-    }
-    if (threadIdx.x == 64) {
-        const double mm = axis_ss / a[n2 - 1];
-        a[n2] -= mm * b[n2 - 1];
-        b[n2] -= mm * c[n2 - 1];
-        d[n2] -= mm * d[n2 - 1];
+        const double m2 = axis_ss / a[n2 - 1];
+        a[n2] -= m2 * b[n2 - 1];
+        b[n2] -= m2 * c[n2 - 1];
+        d[n2] -= m2 * d[n2 - 1];
     }
     __syncthreads();
-    pcr_solve<K, NT>(a, b, c, d, L, L);
-    for (int j = threadIdx.x; j < L; j += NT) ut[base + j] = d[j] * rcp64(b[j]);
+    tri_solve<P, NT>(a, b, c, d, L);
+    for (int j = threadIdx.x; j < L; j += NT) ut[base + j] = d[j];
 }
 
 // Block sum of a per-thread value (fixed order), written by thread 0.
@@ -485,13 +559,35 @@ k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double
 
 // Start of a solve: grains other than `only` (if >= 0) are excluded from it.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_mg_reset(MGState* __restrict__ ms, int ngrains, int only) {
+k_mg_reset(MGState* __restrict__ ms, int ngrains, int only, int in_step) {
     for (int g = threadIdx.x; g < ngrains; g += MG_BLOCK) {
+        const bool solved = only < 0 || g == only;
         ms[g].r2 = 0.0;
         ms[g].b2 = 0.0;
         ms[g].cycles = 0;
-        ms[g].done = (only >= 0 && g != only) ? 1 : 0;
+        ms[g].done = solved ? 0 : 1;
+        // an in-step solve leaves a history to extrapolate from; a standalone
+        // solve (a new density or new particles) starts a new one
+        if (in_step) ms[g].extrap = 1;
+        else if (solved) ms[g].extrap = 0;
     }
+}
+
+// Initial guess of an in-step solve, linear extrapolation in time from the
+// last two solutions: u <- 2 u - uprev, uprev <- u (the time step is fixed).
+// Without a history (first in-step solve after a standalone one) the guess is
+// the last solution and the history starts.  Dirichlet nodes are set again
+// afterwards.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_extrapolate(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
+    const MGDesc& D = lv[blockIdx.y];
+    const int o = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (D.n1 == 0 || o >= D.nodes) return;
+    const gptr<double> u = gbl(D.u);
+    const gptr<double> up = gbl(D.uprev);
+    const double t = u[o];
+    if (ms[blockIdx.y].extrap) u[o] = 2.0 * t - up[o];
+    up[o] = t;
 }
 
 // Sum of nb partial sums in a fixed order (one workgroup).
@@ -691,7 +787,7 @@ static void relax_st(apic_ctx* ctx, int l) {
     const int Lx2 = mn2 + 1;
     const int lines = ctx->lvl_lines_x2[l];   // x2 lines of one colour, summed over grains
     int lpb = 4;
-    while (lpb > 1 && (4 * sizeof(double) * (size_t)lpb * Lx2 > 65536 || lpb * Lx2 > 8 * 256 ||
+    while (lpb > 1 && (4 * sizeof(double) * (size_t)lpb * Lx2 > 61440 || lpb * Lx2 > 8 * 256 ||
                        lines / lpb < 2 * ctx->num_cus))
         lpb >>= 1;
     for (int color = 0; color < 2; ++color) {
@@ -709,24 +805,29 @@ static void transpose(apic_ctx* ctx) {
     hipLaunchKernelGGL(k_transpose<WHICH>, dim3(tiles, G), dim3(256), 0, ctx->stream, ctx->mgdesc, ctx->mgs);
 }
 
-template <int K, int NT>
-static void relax_x2t_launch(apic_ctx* ctx, int color) {
-    const int G = (int)ctx->grains.size();
-    const int lines = (ctx->lvl_max_n1[0] - 1 - color + 1) / 2;
-    const size_t lds = 4 * sizeof(double) * (size_t)(ctx->lvl_max_n2[0] + 1);
-    hipLaunchKernelGGL((k_relax_x2t<K, NT>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream, ctx->mgdesc,
-                       ctx->mgs, color);
+// Shape of the partition solver for `total` equations per workgroup: NT
+// threads of P equations each (line lengths are bounded by the grid limits,
+// at most 2048 equations).
+template <template <int, int> class Launch, class... Args>
+static void with_tri_shape(int total, Args... args) {
+    if (total <= 64 * 3) Launch<3, 64>::run(args...);
+    else if (total <= 64 * 5) Launch<5, 64>::run(args...);
+    else if (total <= 64 * 9) Launch<9, 64>::run(args...);
+    else if (total <= 128 * 9) Launch<9, 128>::run(args...);
+    else Launch<17, 128>::run(args...);
 }
 
-template <int NT>
-static void relax_x2t_k(apic_ctx* ctx, int color) {
-    switch (pcr_k(ctx->lvl_max_n2[0] + 1, NT)) {
-        case 1: relax_x2t_launch<1, NT>(ctx, color); break;
-        case 2: relax_x2t_launch<2, NT>(ctx, color); break;
-        case 4: relax_x2t_launch<4, NT>(ctx, color); break;
-        default: relax_x2t_launch<8, NT>(ctx, color); break;
+template <int P, int NT>
+struct RelaxX2T {
+    static void run(apic_ctx* ctx, int color) {
+        const int G = (int)ctx->grains.size();
+        const int lines = (ctx->lvl_max_n1[0] - 1 - color + 1) / 2;
+        const int L = ctx->lvl_max_n2[0] + 1;
+        const size_t lds = 4 * sizeof(double) * (size_t)std::max(L, 2 * NT);
+        hipLaunchKernelGGL((k_relax_x2t<P, NT>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream, ctx->mgdesc,
+                           ctx->mgs, color);
     }
-}
+};
 
 // The finest level's operator is evaluated at the nodes (its x2 sweeps on the
 // transposed copies), the coarse ones are stored.
@@ -744,10 +845,7 @@ static void relax(apic_ctx* ctx, int l) {
         else relax_x1_k<256, FineStencil>(ctx, 0, color);
     }
     transpose<0>(ctx);
-    for (int color = 0; color < 2; ++color) {
-        if (ctx->lvl_max_n2[0] + 1 > 512) relax_x2t_k<512>(ctx, color);
-        else relax_x2t_k<256>(ctx, color);
-    }
+    for (int color = 0; color < 2; ++color) with_tri_shape<RelaxX2T>(ctx->lvl_max_n2[0] + 1, ctx, color);
     transpose<1>(ctx);
 }
 
@@ -779,14 +877,20 @@ static void check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
 // Start of a solve on the current right-hand side (Dirichlet values already
 // set): |D^-1 b|^2, the initial residual, and the check (grains that already
 // meet the tolerance are done).
-hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain) {
+hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step) {
     const int G = (int)ctx->grains.size();
-    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, G, only_grain);
+    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, G, only_grain, (int)in_step);
     hipLaunchKernelGGL(k_rhs_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
                        ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
     residual_norm(ctx);
     check(ctx, tol, 0, true);
     if (ctx->x2_transposed) transpose<2>(ctx);
+    return hipGetLastError();
+}
+
+hipError_t mg_extrapolate(apic_ctx* ctx) {
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL(k_extrapolate, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgs);
     return hipGetLastError();
 }
 
