@@ -62,7 +62,7 @@ typedef struct {
     double e_bind;     /* energy per absorbed particle besides kinetic, units Te   */
     double weight;     /* macro-particle weight, units n0 R0^3; 0: n V / n_macro   */
     int64_t n_macro;   /* particles of the initial volume load                     */
-    int64_t capacity;  /* particle slots on the device; 0: 1.5 n_macro + 4096      */
+    int64_t capacity;  /* particle slots on the device (below 2^30); 0: 1.5 n_macro + 4096 */
 } apic_species;
 
 /* One grain and its plasma (eqs. 1-2 and Section 2). */

@@ -279,6 +279,7 @@ void free_ctx(apic_ctx* ctx) {
         if (p) (void)hipFree(p);
     };
     F(ctx->tasks);
+    F(ctx->inj_block_task);
     F(ctx->chunk_prefix);
     F(ctx->gdesc);
     F(ctx->mgdesc);
@@ -406,9 +407,9 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
         g.inj_inc[s] = (uint64_t)std::llround(n_real * 4294967296.0);
         int64_t cap = a.capacity;
         if (cap == 0) cap = (int64_t)(1.5 * (double)a.n_macro) + 64 * (int64_t)std::ceil(n_real) + 4096;
-        if (cap > (int64_t)2000000000) {
+        if (cap >= ((int64_t)1 << 30)) {   // the FP32 kernels address slots with 32-bit byte offsets
             hs.rc = APIC_ERANGE;
-            hs.err = "particle capacity above 2^31";
+            hs.err = "particle capacity of 2^30 or more";
             return;
         }
         g.capacity[s] = cap;
@@ -523,7 +524,7 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
 // Per-task view of the ensemble for the particle kernels.
 void fill_tasks(apic_ctx* ctx) {
     ctx->tasks_h.clear();
-    ctx->max_inj_bound = 0;
+    ctx->inj_blocks = 0;
     ctx->max_ntiles = 0;
     ctx->max_sort_blocks = 0;
     ctx->max_segs = 1;
@@ -550,8 +551,11 @@ void fill_tasks(apic_ctx* ctx) {
             t.ns = g.ns;
             t.grain = (int)gi;
             t.sort_blocks = g.sort_blocks[s];
+            // a step injects at most floor(inj_inc / 2^32) + 1 particles: one
+            // thread each, the tasks' workgroups laid end to end
+            t.inj_block0 = ctx->inj_blocks;
+            ctx->inj_blocks += (int)((((g.inj_inc[s] >> 32) + 1) + INJ_BLOCK - 1) / INJ_BLOCK);
             ctx->tasks_h.push_back(t);
-            ctx->max_inj_bound = std::max<int>(ctx->max_inj_bound, (int)(g.inj_inc[s] >> 32) + 1);
             ctx->max_ntiles = std::max(ctx->max_ntiles, g.gp.ntiles);
             ctx->max_sort_blocks = std::max(ctx->max_sort_blocks, g.sort_blocks[s]);
             const int64_t len = (int64_t)g.gp.ntiles * g.sort_blocks[s];
@@ -576,6 +580,15 @@ int build_tables(apic_ctx* ctx) {
     TRY(alloc_t(ctx, &ctx->tasks, ctx->tasks_h.size()));
     TRY(alloc_t(ctx, &ctx->chunk_prefix, ctx->tasks_h.size() + 1));
     TRY(upload_tasks(ctx));
+    {
+        std::vector<int> bt(std::max(ctx->inj_blocks, 1), 0);
+        for (int t = 0; t < ctx->ntasks; ++t) {
+            const int end = t + 1 < ctx->ntasks ? ctx->tasks_h[t + 1].inj_block0 : ctx->inj_blocks;
+            for (int b = ctx->tasks_h[t].inj_block0; b < end; ++b) bt[b] = t;
+        }
+        TRY(alloc_t(ctx, &ctx->inj_block_task, bt.size()));
+        HIPCHK(ctx, hipMemcpy(ctx->inj_block_task, bt.data(), sizeof(int) * bt.size(), hipMemcpyHostToDevice));
+    }
 
     ctx->gdesc_h.assign(G, GrainDesc());
     ctx->n_levels = 0;

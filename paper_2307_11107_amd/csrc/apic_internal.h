@@ -22,6 +22,8 @@
 
 namespace apic {
 
+constexpr int INJ_BLOCK = 256;     // threads per injection workgroup (one particle each)
+
 // Per-species parameters seen by the kernels.
 struct SpeciesParams {
     double q, m, T, w;          // charge (e), mass (me), temperature (Te), weight
@@ -93,6 +95,7 @@ struct PushTask {
     int64_t capacity;
     uint64_t inj_inc;           // particles injected per step, 2^-32 units
     int s, ns, grain, sort_blocks;
+    int inj_block0;             // first workgroup of this task in the injection launch
 };
 
 // One grain, as the field kernels see it.
@@ -236,7 +239,8 @@ struct apic_ctx {
     double* norm_part = nullptr;            // [2][grains][blocks] partial norms (r, b)
     apic::MGBatch* mgb = nullptr;
     apic::MGBatch* mgb_host = nullptr;      // pinned
-    int max_inj_bound = 0;                  // largest per-step injection of any task
+    int inj_blocks = 0;                     // workgroups of the injection launch (all tasks)
+    int* inj_block_task = nullptr;          // [inj_blocks] task of each injection workgroup
     int max_ntiles = 0, max_sort_blocks = 0, max_segs = 0;
     int max_nodes = 0, max_n1 = 0, max_n2 = 0;
     bool x2_transposed = false;             // finest-level x2 sweeps on transposed copies

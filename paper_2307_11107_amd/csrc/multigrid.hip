@@ -3,7 +3,7 @@
 // The paper solves the finite-difference system by LU (Section 2).  On the GPU
 // the same discrete system is solved by multigrid V-cycles: Galerkin coarse
 // operators (R A P, bilinear P, R = P^T / 4, built on the host), alternating
-// zebra line Gauss-Seidel smoothing (x1-lines, then x2-lines; each line is a
+// zebra line Gauss-Seidel smoothing (x1-, x2-, then x1-lines; each line is a
 // tridiagonal system solved in LDS by parallel cyclic reduction, or, for the
 // many long lines of a large ensemble, by the partition method), and a dense
 // inverse on the coarsest grid (a few hundred to a few thousand nodes).  The operator's
@@ -15,6 +15,8 @@
 // hierarchy is shallower, or whose solve has converged, leave at once.  A
 // V-cycle ends with the row-scaled residual norm and a convergence check on
 // the device, so cycles can be replayed from a graph without host reads.
+#include <type_traits>
+
 #include "apic_internal.h"
 #include "device_common.h"
 
@@ -264,6 +266,10 @@ __device__ inline int xcd_line() {
 }
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
+// On the finest level the axis rows j = 0 and j = n2 also couple to the rows
+// two away (one-sided d/dx2), which have their colour; they are relaxed as a
+// third colour after the other two, so that no line reads a line that is being
+// rewritten by the same launch.
 template <int K, int NT, class ST>
 __global__ void __launch_bounds__(NT)
 k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
@@ -271,8 +277,20 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     const MGDesc& D = lv[blockIdx.y];
     if (!level_active(D, ms)) return;
     const int n1 = D.n1, n2 = D.n2;
-    const int j = color + 2 * xcd_line();
-    if (j > n2) return;
+    int j;
+    if constexpr (std::is_same<ST, FineStencil>::value) {
+        const int line = xcd_line();
+        if (color == 2) {
+            if (line > 1) return;
+            j = line == 0 ? 0 : n2;
+        } else {
+            j = color + 2 * line;
+            if (j == 0 || j >= n2) return;
+        }
+    } else {
+        j = color + 2 * xcd_line();
+        if (j > n2) return;
+    }
     const int L = n1 - 1;
     double* a = lds;
     double* b = a + L;
@@ -499,22 +517,30 @@ __device__ inline double block_sum(double v) {
     return t;
 }
 
+// Sum of nb partial sums in a fixed order (one workgroup).
+__device__ inline double sum_parts(const double* __restrict__ p, int nb) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += MG_BLOCK) v += p[k];
+    return block_sum(v);
+}
+
 // |D^-1 (f - A u)|^2 over the unknown nodes of the finest level (D = diagonal
-// of A, lv = the finest level): the operator's rows differ in scale by ~r^4, and the row-scaled norm
-// weighs every node alike.  One partial sum per workgroup, part[grain][block];
-// the check adds them in a fixed order, so a solve is reproducible bit for bit.
+// of A, lv = the finest level): the operator's rows differ in scale by ~r^4,
+// and the row-scaled norm weighs every node alike.  One partial sum per
+// workgroup, part[grain][block]; the batch counters of the check that follows
+// are cleared here.
 __global__ void __launch_bounds__(MG_BLOCK)
-k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part) {
-    const MGDesc& D = lv[blockIdx.y];
-    double* out = part + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (D.n1 == 0 || ms[blockIdx.y].done || (int)(blockIdx.x * MG_BLOCK) >= D.nodes) {
-        if (threadIdx.x == 0) *out = 0.0;
-        return;
+k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part,
+                MGBatch* __restrict__ mb) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        mb->pending = 0;
+        mb->max_cycles = 0;
     }
-    const int n1 = D.n1, n2 = D.n2, nx = n1 + 1;
-    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    const MGDesc& D = lv[blockIdx.y];
     double rr = 0.0;
-    if (idx < D.nodes) {
+    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (D.n1 != 0 && !ms[blockIdx.y].done && idx < D.nodes) {
+        const int n1 = D.n1, n2 = D.n2, nx = n1 + 1;
         const int j = idx / nx, i = idx - j * nx;
         if (i > 0 && i < n1) {
             const FineStencil st(D);
@@ -530,9 +556,42 @@ k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, d
         }
     }
     const double t = block_sum(rr);
-    if (threadIdx.x == 0) *out = t;
+    if (threadIdx.x == 0) gbl(part)[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
+// Per grain (blockIdx.x): its partial norms added in a fixed order (so a solve
+// is reproducible bit for bit), then the convergence check: the grain is done
+// once |D^-1 r| <= tol |D^-1 b| (b with the boundary coupling) or when its
+// residual is not finite.  part_b (the right-hand side's partials, at the start
+// of a solve) is summed into b2 when given; count_cycle marks the check that
+// ends a V-cycle.  The batch counters (grains pending, largest cycle count, a
+// non-finite residual) gather the grains' states by atomics.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_mg_sum_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int nb, const double* __restrict__ part,
+               const double* __restrict__ part_b, double tol2, int count_cycle, MGBatch* __restrict__ mb) {
+    const int g = blockIdx.x;
+    MGState& m = ms[g];
+    if (!m.done) {
+        const double r2 = sum_parts(part + (size_t)g * nb, nb);
+        const double b2 = part_b ? sum_parts(part_b + (size_t)g * nb, nb) : 0.0;
+        if (threadIdx.x == 0) {
+            if (part_b) m.b2 = b2;
+            m.r2 = r2;
+            m.last_r2 = r2;
+            if (count_cycle) m.cycles += 1;
+            if (!(r2 == r2) || !(m.b2 == m.b2)) {
+                atomicOr(&mb->nan, 1);
+                m.done = 1;
+            } else if (r2 <= tol2 * (m.b2 + gd[g].bnd2)) {
+                m.done = 1;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (!m.done) atomicAdd(&mb->pending, 1);
+        atomicMax(&mb->max_cycles, m.cycles);
+    }
+}
 // |D^-1 f|^2 over the unknown nodes, partial sums as above
 __global__ void __launch_bounds__(MG_BLOCK)
 k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part) {
@@ -590,55 +649,6 @@ k_extrapolate(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
     up[o] = t;
 }
 
-// Sum of nb partial sums in a fixed order (one workgroup).
-__device__ inline double sum_parts(const double* __restrict__ p, int nb) {
-    double v = 0.0;
-    for (int k = threadIdx.x; k < nb; k += MG_BLOCK) v += p[k];
-    return block_sum(v);
-}
-
-// Per grain (blockIdx.x), the partial norms of the grain summed in a fixed
-// order: ms.r2 (and, at the start of a solve, ms.b2).
-__global__ void __launch_bounds__(MG_BLOCK)
-k_mg_sum(MGState* __restrict__ ms, int nb, const double* __restrict__ part_r, const double* __restrict__ part_b) {
-    const int g = blockIdx.x;
-    if (ms[g].done) return;
-    const double r2 = sum_parts(part_r + (size_t)g * nb, nb);
-    double b2 = 0.0;
-    if (part_b) b2 = sum_parts(part_b + (size_t)g * nb, nb);
-    if (threadIdx.x == 0) {
-        ms[g].r2 = r2;
-        if (part_b) ms[g].b2 = b2;
-    }
-}
-
-// Convergence check after the residual norms: a grain is done once
-// |D^-1 r| <= tol |D^-1 b| (b with the boundary coupling) or when its residual
-// is not finite; count_cycle marks the check that ends a V-cycle.  One thread.
-__global__ void k_mg_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int ngrains, double tol2,
-                           int count_cycle, MGBatch* __restrict__ mb) {
-    if (threadIdx.x != 0) return;
-    int pending = 0, nan = mb->nan, maxc = 0;
-    for (int g = 0; g < ngrains; ++g) {
-        MGState& m = ms[g];
-        if (!m.done) {
-            const double r2 = m.r2;
-            m.last_r2 = r2;
-            if (count_cycle) m.cycles += 1;
-            if (!(r2 == r2) || !(m.b2 == m.b2)) {
-                nan = 1;
-                m.done = 1;
-            } else if (r2 <= tol2 * (m.b2 + gd[g].bnd2)) {
-                m.done = 1;
-            }
-        }
-        pending += m.done ? 0 : 1;
-        maxc = max(maxc, m.cycles);
-    }
-    mb->pending = pending;
-    mb->nan = nan;
-    mb->max_cycles = maxc;
-}
 
 // Coarse right-hand side fc = P^T (f - A u) / 4 on the coarse unknowns, the
 // fine residuals formed on the fly (full weighting without rows outside the
@@ -739,7 +749,7 @@ template <int K, int NT, class ST>
 static void relax_x1_launch(apic_ctx* ctx, int l, int color) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     const size_t lds = 4 * sizeof(double) * (size_t)(mn1 - 1);
-    const int lines = (mn2 + 1 - color + 1) / 2;
+    const int lines = color == 2 ? 2 : (mn2 + 1 - color + 1) / 2;
     const int G = (int)ctx->grains.size();
     hipLaunchKernelGGL((k_relax_x1<K, NT, ST>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
                        ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
@@ -777,14 +787,21 @@ static void relax_x2_k(apic_ctx* ctx, int l, int color) {
     }
 }
 
+// Both colours of the x1-line sweep of level l (on the finest level, then the
+// two axis rows).
 template <class ST>
-static void relax_st(apic_ctx* ctx, int l) {
-    const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
-    for (int color = 0; color < 2; ++color) {
-        if (mn1 - 1 > 512) relax_x1_k<512, ST>(ctx, l, color);
+static void sweep_x1(apic_ctx* ctx, int l) {
+    const int colors = std::is_same<ST, FineStencil>::value ? 3 : 2;
+    for (int color = 0; color < colors; ++color) {
+        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<512, ST>(ctx, l, color);
         else relax_x1_k<256, ST>(ctx, l, color);
     }
-    const int Lx2 = mn2 + 1;
+}
+
+// Both colours of the x2-line sweep of level l (lines read in place).
+template <class ST>
+static void sweep_x2(apic_ctx* ctx, int l) {
+    const int Lx2 = ctx->lvl_max_n2[l] + 1;
     const int lines = ctx->lvl_lines_x2[l];   // x2 lines of one colour, summed over grains
     int lpb = 4;
     while (lpb > 1 && (4 * sizeof(double) * (size_t)lpb * Lx2 > 61440 || lpb * Lx2 > 8 * 256 ||
@@ -793,7 +810,7 @@ static void relax_st(apic_ctx* ctx, int l) {
     for (int color = 0; color < 2; ++color) {
         if (lpb == 4) relax_x2_k<4, 256, ST>(ctx, l, color);
         else if (lpb == 2) relax_x2_k<2, 256, ST>(ctx, l, color);
-        else if (Lx2 > 512) relax_x2_k<1, 512, ST>(ctx, l, color);
+        else if (Lx2 > 256) relax_x2_k<1, 512, ST>(ctx, l, color);
         else relax_x2_k<1, 256, ST>(ctx, l, color);
     }
 }
@@ -829,24 +846,34 @@ struct RelaxX2T {
     }
 };
 
-// The finest level's operator is evaluated at the nodes (its x2 sweeps on the
-// transposed copies), the coarse ones are stored.
-static void relax(apic_ctx* ctx, int l) {
+// Smoothing of level l after its coarse-grid correction: x1 lines, x2 lines,
+// x1 lines (each sweep both colours).  No smoothing precedes the restriction
+// (a sawtooth cycle): on these operators that converges per cycle about as
+// fast as one alternating sweep before and after the correction, with six
+// sweep launches per level instead of eight.  The finest level's operator is
+// evaluated at the nodes (its x2 sweeps on the transposed copies when the
+// level is large), the coarse ones are stored.
+template <class ST>
+static void smooth_st(apic_ctx* ctx, int l) {
+    sweep_x1<ST>(ctx, l);
+    sweep_x2<ST>(ctx, l);
+    sweep_x1<ST>(ctx, l);
+}
+
+static void smooth(apic_ctx* ctx, int l) {
     if (l > 0) {
-        relax_st<StoredStencil>(ctx, l);
+        smooth_st<StoredStencil>(ctx, l);
         return;
     }
     if (!ctx->x2_transposed) {
-        relax_st<FineStencil>(ctx, 0);
+        smooth_st<FineStencil>(ctx, 0);
         return;
     }
-    for (int color = 0; color < 2; ++color) {
-        if (ctx->lvl_max_n1[0] - 1 > 512) relax_x1_k<512, FineStencil>(ctx, 0, color);
-        else relax_x1_k<256, FineStencil>(ctx, 0, color);
-    }
+    sweep_x1<FineStencil>(ctx, 0);
     transpose<0>(ctx);
     for (int color = 0; color < 2; ++color) with_tri_shape<RelaxX2T>(ctx->lvl_max_n2[0] + 1, ctx, color);
     transpose<1>(ctx);
+    sweep_x1<FineStencil>(ctx, 0);
 }
 
 static void coarse_solve(apic_ctx* ctx, int l) {
@@ -859,19 +886,17 @@ static void coarse_solve(apic_ctx* ctx, int l) {
 
 static int norm_blocks(apic_ctx* ctx) { return (ctx->lvl_max_nodes[0] + MG_BLOCK - 1) / MG_BLOCK; }
 
-static void residual_norm(apic_ctx* ctx) {
-    const int G = (int)ctx->grains.size();
-    hipLaunchKernelGGL(k_residual_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream,
-                       ctx->mgdesc, ctx->mgs, ctx->norm_part);
-}
-
-static void check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
+// Residual norm of the finest level, then its per-grain sums and the
+// convergence check (the right-hand side's partials are summed too at the start
+// of a solve).
+static void residual_check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
     const int G = (int)ctx->grains.size();
     const int nb = norm_blocks(ctx);
-    hipLaunchKernelGGL(k_mg_sum, dim3(G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, nb, ctx->norm_part,
-                       with_b ? ctx->norm_part + (size_t)G * nb : nullptr);
-    hipLaunchKernelGGL(k_mg_check, dim3(1), dim3(64), 0, ctx->stream, ctx->mgs, ctx->gdesc, G, tol * tol,
-                       count_cycle, ctx->mgb);
+    hipLaunchKernelGGL(k_residual_norm, dim3(nb, G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgs,
+                       ctx->norm_part, ctx->mgb);
+    hipLaunchKernelGGL(k_mg_sum_check, dim3(G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, ctx->gdesc, nb,
+                       ctx->norm_part, with_b ? ctx->norm_part + (size_t)G * nb : nullptr, tol * tol, count_cycle,
+                       ctx->mgb);
 }
 
 // Start of a solve on the current right-hand side (Dirichlet values already
@@ -882,8 +907,7 @@ hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step) {
     hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, G, only_grain, (int)in_step);
     hipLaunchKernelGGL(k_rhs_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
                        ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
-    residual_norm(ctx);
-    check(ctx, tol, 0, true);
+    residual_check(ctx, tol, 0, true);
     if (ctx->x2_transposed) transpose<2>(ctx);
     return hipGetLastError();
 }
@@ -894,13 +918,14 @@ hipError_t mg_extrapolate(apic_ctx* ctx) {
     return hipGetLastError();
 }
 
-// One V-cycle of every grain not yet done, then the residual norm and the check.
+// One V-cycle (sawtooth: restriction of the current residual down to the
+// coarsest level, then correction and smoothing on the way up) of every grain
+// not yet done, then the residual norm and the check.
 hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
     const int G = (int)ctx->grains.size();
     const int nl = ctx->n_levels;
     coarse_solve(ctx, 0);
     for (int l = 0; l + 1 < nl; ++l) {
-        relax(ctx, l);
         const int cn = ctx->lvl_max_nodes[l + 1];
         if (l == 0)
             hipLaunchKernelGGL(k_restrict_residual<FineStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
@@ -916,10 +941,9 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
         hipLaunchKernelGGL(k_prolong_add, dim3((fn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
                            ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
                            ctx->mgs);
-        relax(ctx, l);
+        smooth(ctx, l);
     }
-    residual_norm(ctx);
-    check(ctx, tol, 1, false);
+    residual_check(ctx, tol, 1, false);
     return hipGetLastError();
 }
 

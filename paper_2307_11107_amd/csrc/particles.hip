@@ -156,14 +156,25 @@ struct SplitState {
     float f1, f2, vR, vZ, vT;
 };
 
+// Slot p of a 4-byte particle array, addressed as the array base plus a
+// 32-bit byte offset (a task holds fewer than 2^30 slots): the loads and
+// stores then take the base from scalar registers and share one offset
+// register instead of forming a 64-bit address per array.
+template <typename T>
+__device__ __forceinline__ gptr<T> slot4(T* base, int64_t p) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return (gptr<T>)((gptr<C>)gbl(reinterpret_cast<C*>(base)) + ((uint32_t)p << 2));
+}
+
 __device__ inline SplitState load_split(const PBuf& b, int64_t p) {
     SplitState q;
-    q.c = gbl(static_cast<const int32_t*>(b.pos0))[p];
-    q.f1 = gbl(static_cast<const float*>(b.pos1))[p];
-    q.f2 = gbl(static_cast<const float*>(b.pos2))[p];
-    q.vR = gbl(static_cast<const float*>(b.vR))[p];
-    q.vZ = gbl(static_cast<const float*>(b.vZ))[p];
-    q.vT = gbl(static_cast<const float*>(b.vT))[p];
+    q.c = *slot4(static_cast<const int32_t*>(b.pos0), p);
+    q.f1 = *slot4(static_cast<const float*>(b.pos1), p);
+    q.f2 = *slot4(static_cast<const float*>(b.pos2), p);
+    q.vR = *slot4(static_cast<const float*>(b.vR), p);
+    q.vZ = *slot4(static_cast<const float*>(b.vZ), p);
+    q.vT = *slot4(static_cast<const float*>(b.vT), p);
     return q;
 }
 
@@ -179,12 +190,7 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
                                      int& i2n, float& f1n, float& f2n) {
     const int32_t c = q.c;
     if (c < 0) return -1;
-    const gptr<int32_t> cell = gbl(static_cast<int32_t*>(b.pos0));
-    const gptr<float> f1a = gbl(static_cast<float*>(b.pos1));
-    const gptr<float> f2a = gbl(static_cast<float*>(b.pos2));
-    const gptr<float> vRa = gbl(static_cast<float*>(b.vR));
-    const gptr<float> vZa = gbl(static_cast<float*>(b.vZ));
-    const gptr<float> vTa = gbl(static_cast<float*>(b.vT));
+    const gptr<int32_t> cell = slot4(static_cast<int32_t*>(b.pos0), p);
     const int n1 = K.n1, n2 = K.n2, nx = K.nx;
     const float alpha = K.alpha, h1 = K.h1, h2 = K.h2, qmh = K.qmh, step = K.step;
     const int i1 = cell_i1(c), i2 = cell_i2(c);
@@ -296,19 +302,19 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
         const float t_in = tmid > 0.f ? tmid : 1.f;
         tally_impact<float>(gp.alpha, gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
                             dY, dZ, t_in, vR, vZ, vT, tally, tally_count, 24);
-        cell[p] = DEAD;
+        *cell = DEAD;
         return 1;
     }
     if (i1n >= n1) {
-        cell[p] = DEAD;
+        *cell = DEAD;
         return 2;
     }
-    cell[p] = pack_cell(i1n, i2n);
-    f1a[p] = f1n;
-    f2a[p] = f2n;
-    vRa[p] = vRn;
-    vZa[p] = vZ;
-    vTa[p] = vTn;
+    *cell = pack_cell(i1n, i2n);
+    *slot4(static_cast<float*>(b.pos1), p) = f1n;
+    *slot4(static_cast<float*>(b.pos2), p) = f2n;
+    *slot4(static_cast<float*>(b.vR), p) = vRn;
+    *slot4(static_cast<float*>(b.vZ), p) = vZ;
+    *slot4(static_cast<float*>(b.vT), p) = vTn;
     return 0;
 }
 
@@ -748,8 +754,13 @@ __device__ inline void load_task(const PushTask* __restrict__ tasks, const int64
     v.dep = deposit ? static_cast<T*>(task.dep) : nullptr;
     v.tally = task.tally;
     v.tally_count = task.tally_count;
-    v.n = v.ctr->n[v.s];
-    v.b = task.buf[v.ctr->cur[v.s]];
+    // the live count and buffer index come from memory this kernel also
+    // writes (vector loads); they are the same in every lane, and reading them
+    // into scalar registers keeps the task's array bases scalar as well
+    const int64_t n = v.ctr->n[v.s];
+    v.n = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(n >> 32)) << 32) |
+                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)n));
+    v.b = task.buf[__builtin_amdgcn_readfirstlane(v.ctr->cur[v.s])];
 }
 
 __device__ inline void flush_counts(DevCounters* ctr, int s, uint32_t& n_live, uint32_t& n_abs, uint32_t& n_esc) {
@@ -769,7 +780,7 @@ struct SplitKey { int32_t c; };
 struct PlainKey { double x1, x2; };
 
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, SplitKey& k) {
-    k.c = p < n ? gbl(static_cast<const int32_t*>(b.pos0))[p] : DEAD;
+    k.c = p < n ? *slot4(static_cast<const int32_t*>(b.pos0), p) : DEAD;
 }
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, PlainKey& k) {
     if (p < n) {
@@ -798,11 +809,11 @@ __device__ inline bool key_cell(const GrainParams& gp, const PlainKey& k, int& i
 // need not wait for the key
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, SplitState& q) {
     if (p >= n) return;
-    q.f1 = gbl(static_cast<const float*>(b.pos1))[p];
-    q.f2 = gbl(static_cast<const float*>(b.pos2))[p];
-    q.vR = gbl(static_cast<const float*>(b.vR))[p];
-    q.vZ = gbl(static_cast<const float*>(b.vZ))[p];
-    q.vT = gbl(static_cast<const float*>(b.vT))[p];
+    q.f1 = *slot4(static_cast<const float*>(b.pos1), p);
+    q.f2 = *slot4(static_cast<const float*>(b.pos2), p);
+    q.vR = *slot4(static_cast<const float*>(b.vR), p);
+    q.vZ = *slot4(static_cast<const float*>(b.vZ), p);
+    q.vT = *slot4(static_cast<const float*>(b.vT), p);
 }
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainState& q) {
     if (p >= n) return;
@@ -1109,10 +1120,13 @@ k_inject_plan(const PushTask* __restrict__ tasks, int ntasks) {
 // Flux-Maxwellian injection at x1_out: x2 with density proportional to eq. (4),
 // inward normal speed Rayleigh(sigma), tangential normal(0, sigma^2), then a
 // straight partial step U * dt with the usual boundary tests; the survivors
-// deposit their charge.  Slot = base + k, id = id0 + k; blockIdx.y = task.
-__global__ void __launch_bounds__(BLOCK)
-k_inject(const PushTask* __restrict__ tasks, bool split, int deposit) {
-    const PushTask& T = tasks[blockIdx.y];
+// deposit their charge.  Slot = base + k, id = id0 + k.  One thread per
+// particle; the tasks' workgroups are laid end to end (block_task), each task
+// with as many as its largest injection needs, so small tasks launch no idle
+// workgroups.
+__global__ void __launch_bounds__(INJ_BLOCK)
+k_inject(const PushTask* __restrict__ tasks, const int* __restrict__ block_task, bool split, int deposit) {
+    const PushTask& T = tasks[block_task[blockIdx.x]];
     const GrainParams gp = T.gp;
     const SpeciesParams sp = T.sp;
     DevCounters* ctr = T.ctr;
@@ -1127,8 +1141,9 @@ k_inject(const PushTask* __restrict__ tasks, bool split, int deposit) {
     unsigned long long* tally_count = T.tally_count;
     const double alpha = gp.alpha, xo = gp.x1_out;
     uint32_t n_abs = 0, n_esc = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_new;
-         k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k0 = (int64_t)(blockIdx.x - T.inj_block0) * INJ_BLOCK;
+    const int64_t k_end = k0 + INJ_BLOCK < n_new ? k0 + INJ_BLOCK : n_new;
+    for (int64_t k = k0 + threadIdx.x; k < k_end; k += INJ_BLOCK) {
         const int64_t slot = base + k;
         if (slot >= T.capacity) continue;
         double x2 = 0;
@@ -1557,10 +1572,9 @@ hipError_t launch_deposit(apic_ctx* ctx) {
 
 hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
     hipLaunchKernelGGL(k_inject_plan, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks);
-    const int64_t want = (ctx->max_inj_bound + BLOCK - 1) / BLOCK;
-    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024));
-    hipLaunchKernelGGL(k_inject, dim3(bx, ctx->ntasks), dim3(BLOCK), 0, ctx->stream, ctx->tasks,
-                       is_split(ctx), deposit ? 1 : 0);
+    if (ctx->inj_blocks > 0)
+        hipLaunchKernelGGL(k_inject, dim3(ctx->inj_blocks), dim3(INJ_BLOCK), 0, ctx->stream, ctx->tasks,
+                           ctx->inj_block_task, is_split(ctx), deposit ? 1 : 0);
     return hipGetLastError();
 }
 

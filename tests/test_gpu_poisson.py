@@ -59,3 +59,20 @@ def test_fp32_context_solves_in_fp64():
         apic.apic_free(ctx)
     ref = PoissonSolver(Grid(n1, n2, -0.1, 0.1)).solve(source_from_density(rho, 1.0), -2.5, 0.0)
     assert np.max(np.abs(phi - ref)) / np.max(np.abs(ref)) <= 1e-10
+
+
+def test_solve_is_bitwise_reproducible():
+    """The residual norms are per-workgroup partial sums added in a fixed order
+    by the last workgroup to finish, so the same solve from the same state gives
+    the same bits in two contexts (the 512 x 512 grid has a 65 x 65 dense
+    coarsest level and three levels of line sweeps)."""
+    n1, n2 = 512, 512
+    rho = smooth_density(n1, n2, seed=11, amplitude=1.0)
+    phis = []
+    for _ in range(2):
+        ctx = _ctx(n1, n2, 0.2, -0.1, 1.0)
+        try:
+            phis.append(apic.apic_solve_poisson(ctx, 0, rho, shape=(n2 + 1, n1 + 1)))
+        finally:
+            apic.apic_free(ctx)
+    assert np.array_equal(phis[0], phis[1])
