@@ -375,7 +375,7 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     gp.M_area = bound_outer_area_density(c.x1_out, c.alpha);
     gp.key0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
     gp.key1 = (uint32_t)((c.seed >> 32) + (uint64_t)gi);
-    set_tiles(gp, tile_log2_for(n1, n2, 3));
+    set_tiles(gp, tile_log2_for(n1, n2, Schedule().tile_log2));
 
     node_volumes(n1, n2, c.x1_out, c.alpha, g.vol_host);
     g.V = 0.0;
@@ -551,10 +551,10 @@ void fill_tasks(apic_ctx* ctx) {
             t.ns = g.ns;
             t.grain = (int)gi;
             t.sort_blocks = g.sort_blocks[s];
-            // a step injects at most floor(inj_inc / 2^32) + 1 particles: one
-            // thread each, the tasks' workgroups laid end to end
+            // a step injects at most floor(inj_inc / 2^32) + 1 particles; the
+            // tasks' injection workgroups are laid end to end
             t.inj_block0 = ctx->inj_blocks;
-            ctx->inj_blocks += (int)((((g.inj_inc[s] >> 32) + 1) + INJ_BLOCK - 1) / INJ_BLOCK);
+            ctx->inj_blocks += (int)((((g.inj_inc[s] >> 32) + 1) + INJ_PER_BLOCK - 1) / INJ_PER_BLOCK);
             ctx->tasks_h.push_back(t);
             ctx->max_ntiles = std::max(ctx->max_ntiles, g.gp.ntiles);
             ctx->max_sort_blocks = std::max(ctx->max_sort_blocks, g.sort_blocks[s]);

@@ -22,7 +22,8 @@
 
 namespace apic {
 
-constexpr int INJ_BLOCK = 256;     // threads per injection workgroup (one particle each)
+constexpr int INJ_BLOCK = 256;                  // threads per injection workgroup
+constexpr int INJ_PER_BLOCK = 16 * INJ_BLOCK;   // particles per injection workgroup
 
 // Per-species parameters seen by the kernels.
 struct SpeciesParams {
@@ -194,7 +195,7 @@ struct Grain {
 struct Schedule {
     int push_wg_per_cu = 8;     // persistent push workgroups per compute unit (capped at
                                 // what stays resident)
-    int tile_log2 = 3;          // sort tile edge, log2 cells (capped per grain)
+    int tile_log2 = 4;          // sort tile edge, log2 cells (capped per grain)
     int sort_every = 8;         // steps between sorts
 };
 

@@ -1120,12 +1120,17 @@ k_inject_plan(const PushTask* __restrict__ tasks, int ntasks) {
 // Flux-Maxwellian injection at x1_out: x2 with density proportional to eq. (4),
 // inward normal speed Rayleigh(sigma), tangential normal(0, sigma^2), then a
 // straight partial step U * dt with the usual boundary tests; the survivors
-// deposit their charge.  Slot = base + k, id = id0 + k.  One thread per
-// particle; the tasks' workgroups are laid end to end (block_task), each task
-// with as many as its largest injection needs, so small tasks launch no idle
-// workgroups.
+// deposit their charge.  Slot = base + k, id = id0 + k.  A workgroup takes
+// INJ_PER_BLOCK consecutive particles of one task; the tasks' workgroups are
+// laid end to end (block_task), each task with as many as its largest
+// injection needs.  The injected particles end their partial step within a
+// cell of the outer boundary, so every step's injections deposit onto the same
+// three node columns: a workgroup adds its particles' weights in LDS and then
+// each node once to the global sums, instead of thousands of workgroups'
+// atomics contending on those few hundred nodes.
 __global__ void __launch_bounds__(INJ_BLOCK)
 k_inject(const PushTask* __restrict__ tasks, const int* __restrict__ block_task, bool split, int deposit) {
+    extern __shared__ unsigned char inj_lds[];
     const PushTask& T = tasks[block_task[blockIdx.x]];
     const GrainParams gp = T.gp;
     const SpeciesParams sp = T.sp;
@@ -1141,8 +1146,19 @@ k_inject(const PushTask* __restrict__ tasks, const int* __restrict__ block_task,
     unsigned long long* tally_count = T.tally_count;
     const double alpha = gp.alpha, xo = gp.x1_out;
     uint32_t n_abs = 0, n_esc = 0;
-    const int64_t k0 = (int64_t)(blockIdx.x - T.inj_block0) * INJ_BLOCK;
-    const int64_t k_end = k0 + INJ_BLOCK < n_new ? k0 + INJ_BLOCK : n_new;
+    // node window: columns n1 - 2 .. n1 of every row, [row][3]
+    const int n1 = gp.n1, nx = gp.nx, wn = 3 * (gp.n2 + 1);
+    float* wf = reinterpret_cast<float*>(inj_lds);
+    double* wd = reinterpret_cast<double*>(inj_lds);
+    if (dep) {
+        for (int q = threadIdx.x; q < wn; q += INJ_BLOCK) {
+            if (split) wf[q] = 0.f;
+            else wd[q] = 0.0;
+        }
+        __syncthreads();
+    }
+    const int64_t k0 = (int64_t)(blockIdx.x - T.inj_block0) * INJ_PER_BLOCK;
+    const int64_t k_end = k0 + INJ_PER_BLOCK < n_new ? k0 + INJ_PER_BLOCK : n_new;
     for (int64_t k = k0 + threadIdx.x; k < k_end; k += INJ_BLOCK) {
         const int64_t slot = base + k;
         if (slot >= T.capacity) continue;
@@ -1189,14 +1205,55 @@ k_inject(const PushTask* __restrict__ tasks, const int* __restrict__ block_task,
                 const int32_t c = gbl(static_cast<int32_t*>(b.pos0))[slot];
                 const float f1 = gbl(static_cast<float*>(b.pos1))[slot];
                 const float f2 = gbl(static_cast<float*>(b.pos2))[slot];
-                float* d = static_cast<float*>(dep);
-                const int o = cell_i2(c) * gp.nx + cell_i1(c);
-                gadd(&d[o], (1.f - f1) * (1.f - f2));
-                gadd(&d[o + 1], f1 * (1.f - f2));
-                gadd(&d[o + gp.nx], (1.f - f1) * f2);
-                gadd(&d[o + gp.nx + 1], f1 * f2);
+                const int i1 = cell_i1(c), i2 = cell_i2(c);
+                const float w00 = (1.f - f1) * (1.f - f2), w10 = f1 * (1.f - f2);
+                const float w01 = (1.f - f1) * f2, w11 = f1 * f2;
+                if (i1 >= n1 - 2) {
+                    const int q = 3 * i2 + (i1 - (n1 - 2));
+                    atomicAdd(&wf[q], w00);
+                    atomicAdd(&wf[q + 1], w10);
+                    atomicAdd(&wf[q + 3], w01);
+                    atomicAdd(&wf[q + 4], w11);
+                } else {
+                    float* d = static_cast<float*>(dep);
+                    const int o = i2 * nx + i1;
+                    gadd(&d[o], w00);
+                    gadd(&d[o + 1], w10);
+                    gadd(&d[o + nx], w01);
+                    gadd(&d[o + nx + 1], w11);
+                }
             } else {
-                deposit64(gp, static_cast<double*>(dep), x1n, x2n);
+                int i1, i2;
+                double f1, f2;
+                locate64(gp, x1n, x2n, i1, i2, f1, f2);
+                const double w00 = (1 - f1) * (1 - f2), w10 = f1 * (1 - f2), w01 = (1 - f1) * f2, w11 = f1 * f2;
+                if (i1 >= n1 - 2) {
+                    const int q = 3 * i2 + (i1 - (n1 - 2));
+                    atomicAdd(&wd[q], w00);
+                    atomicAdd(&wd[q + 1], w10);
+                    atomicAdd(&wd[q + 3], w01);
+                    atomicAdd(&wd[q + 4], w11);
+                } else {
+                    double* d = static_cast<double*>(dep);
+                    const int o = i2 * nx + i1;
+                    gadd(&d[o], w00);
+                    gadd(&d[o + 1], w10);
+                    gadd(&d[o + nx], w01);
+                    gadd(&d[o + nx + 1], w11);
+                }
+            }
+        }
+    }
+    if (dep) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < wn; q += INJ_BLOCK) {
+            const int o = (q / 3) * nx + (n1 - 2) + q % 3;
+            if (split) {
+                const float v = wf[q];
+                if (v != 0.f) gadd(&static_cast<float*>(dep)[o], v);
+            } else {
+                const double v = wd[q];
+                if (v != 0.0) gadd(&static_cast<double*>(dep)[o], v);
             }
         }
     }
@@ -1573,7 +1630,8 @@ hipError_t launch_deposit(apic_ctx* ctx) {
 hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
     hipLaunchKernelGGL(k_inject_plan, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks);
     if (ctx->inj_blocks > 0)
-        hipLaunchKernelGGL(k_inject, dim3(ctx->inj_blocks), dim3(INJ_BLOCK), 0, ctx->stream, ctx->tasks,
+        hipLaunchKernelGGL(k_inject, dim3(ctx->inj_blocks), dim3(INJ_BLOCK),
+                           3 * (size_t)(ctx->max_n2 + 1) * (is_split(ctx) ? sizeof(float) : sizeof(double)), ctx->stream, ctx->tasks,
                            ctx->inj_block_task, is_split(ctx), deposit ? 1 : 0);
     return hipGetLastError();
 }
