@@ -490,7 +490,10 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
     HIPCHK(ctx, launch_fill(ctx, g.grad, 2 * fsz * (size_t)g.nodes));
     HIPCHK(ctx, hipMemcpyAsync(g.vol, g.vol_host.data(), sizeof(double) * g.nodes,
                                hipMemcpyHostToDevice, ctx->stream));
-    TRY(alloc_t(ctx, &g.coarse_inv, (size_t)g.coarse_nodes * g.coarse_nodes));
+    // the dense inverse with rows padded to an even length (16-byte aligned rows)
+    const size_t inv_pitch = (size_t)((g.coarse_nodes + 1) & ~1);
+    TRY(alloc_t(ctx, &g.coarse_inv, (size_t)g.coarse_nodes * inv_pitch));
+    HIPCHK(ctx, launch_fill(ctx, g.coarse_inv, sizeof(double) * g.coarse_nodes * inv_pitch));
     std::vector<double> stage;
     g.mg.resize(hs.levels.size());
     for (size_t l = 0; l < hs.levels.size(); ++l) {
@@ -517,7 +520,10 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             std::copy(hs.levels[l].c[k].begin(), hs.levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
         HIPCHK(ctx, hipMemcpy(L.st, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice));
     }
-    HIPCHK(ctx, hipMemcpy(g.coarse_inv, hs.inv.data(), sizeof(double) * hs.inv.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy2DAsync(g.coarse_inv, sizeof(double) * inv_pitch, hs.inv.data(),
+                                 sizeof(double) * g.coarse_nodes, sizeof(double) * g.coarse_nodes, g.coarse_nodes,
+                                 hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return APIC_OK;
 }
 

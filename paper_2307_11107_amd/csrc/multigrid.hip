@@ -711,26 +711,49 @@ k_prolong_add(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse
 // Dense solve on a grain's coarsest level: u = A^-1 rhs with rhs = f on the
 // unknowns and rhs = u on the Dirichlet columns (identity rows of A), so the
 // same kernel serves a correction level (u = 0 there) and a grid that is
-// itself small enough; one wave per unknown row.
+// itself small enough.  The workgroup stages rhs in LDS once; each wave then
+// streams rows of the inverse (rows padded to an even length, read two
+// entries per lane and load).  The kernel writes u only on unknown rows and
+// reads it only on Dirichlet columns.
+constexpr int CS_ROWS = 8;   // rows per workgroup
+
 __global__ void __launch_bounds__(MG_BLOCK)
 k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
+    extern __shared__ double rhs[];
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
     const MGDesc& D = lv[blockIdx.y];
     if (D.n1 == 0 || !D.coarsest || ms[blockIdx.y].done) return;
-    const int m = D.m, nx = D.n1 + 1;
-    const int row = blockIdx.x * (MG_BLOCK / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= m) return;
-    const int ri = row % nx;
-    if (ri == 0 || ri == D.n1) return;
-    const gptr<const double> a = gbl(D.inv + (size_t)row * m);
-    double acc = 0.0;
-    for (int k = lane; k < m; k += 64) {
-        const int i = k % nx;
-        acc += a[k] * ((i == 0 || i == D.n1) ? gbl(D.u)[k] : gbl(D.f)[k]);
+    const int m = D.m, mp = (m + 1) & ~1, nx = D.n1 + 1;
+    const int row0 = blockIdx.x * CS_ROWS;
+    if (row0 >= m) return;
+    const gptr<double> u = gbl(D.u);
+    const gptr<const double> f = gbl(static_cast<const double*>(D.f));
+    for (int k = threadIdx.x; k < mp; k += MG_BLOCK) {
+        double v = 0.0;
+        if (k < m) {
+            const int i = k % nx;
+            v = (i == 0 || i == D.n1) ? u[k] : f[k];
+        }
+        rhs[k] = v;
     }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < CS_ROWS; r += MG_BLOCK / 64) {
+        const int row = row0 + r;
+        if (row >= m) break;
+        const int ri = row % nx;
+        if (ri == 0 || ri == D.n1) continue;
+        const gptr<const dbl2> a = (gptr<const dbl2>)gbl(D.inv + (size_t)row * mp);
+        double acc = 0.0;
+#pragma unroll 4
+        for (int k = lane; k < mp / 2; k += 64) {
+            const dbl2 v = a[k];
+            acc += v.x * rhs[2 * k] + v.y * rhs[2 * k + 1];
+        }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) gbl(D.u)[row] = acc;
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) u[row] = acc;
+    }
 }
 
 // ------------------------------------------------------------------ launches
@@ -880,8 +903,9 @@ static void coarse_solve(apic_ctx* ctx, int l) {
     const int G = (int)ctx->grains.size();
     const int m = ctx->lvl_max_m[l];
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_coarse_solve, dim3((m + MG_BLOCK / 64 - 1) / (MG_BLOCK / 64), G),
-                       dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgs);
+    const size_t lds = sizeof(double) * (size_t)((m + 1) & ~1);
+    hipLaunchKernelGGL(k_coarse_solve, dim3((m + CS_ROWS - 1) / CS_ROWS, G), dim3(MG_BLOCK), lds, ctx->stream,
+                       ctx->mgdesc + (size_t)l * G, ctx->mgs);
 }
 
 static int norm_blocks(apic_ctx* ctx) { return (ctx->lvl_max_nodes[0] + MG_BLOCK - 1) / MG_BLOCK; }
