@@ -270,9 +270,15 @@ __device__ inline int xcd_line() {
 // two away (one-sided d/dx2), which have their colour; they are relaxed as a
 // third colour after the other two, so that no line reads a line that is being
 // rewritten by the same launch.
+// With cl (the next coarser level) the sweep also applies the coarse-grid
+// correction u += P uc: a line's solution does not depend on its own old
+// value, only on its neighbour lines, so the first colour of the first sweep
+// after the correction reads its two neighbour rows prolonged (bilinear P) and
+// the other rows never need the correction added before they are solved.
 template <int K, int NT, class ST>
 __global__ void __launch_bounds__(NT)
-k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color) {
+k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color,
+           const MGDesc* __restrict__ cl) {
     extern __shared__ double lds[];
     const MGDesc& D = lv[blockIdx.y];
     if (!level_active(D, ms)) return;
@@ -285,7 +291,24 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
             j = line == 0 ? 0 : n2;
         } else {
             j = color + 2 * line;
-            if (j == 0 || j >= n2) return;
+            if (j == 0 || j >= n2) {
+                // the axis rows are solved after the odd rows, which read
+                // them: a prolonging launch applies their correction here
+                // (no line of this launch reads them)
+                if (color == 0 && line == 0 && cl != nullptr && cl[blockIdx.y].n1 != 0) {
+                    const MGDesc& C = cl[blockIdx.y];
+                    const int nx = n1 + 1, ncx = C.n1 + 1, n2c = C.n2;
+                    const gptr<double> u = gbl(D.u);
+                    const gptr<const double> uc = gbl(static_cast<const double*>(C.u));
+                    for (int t = threadIdx.x; t < 2 * nx; t += NT) {
+                        const int top = t >= nx, i = top ? t - nx : t;
+                        const int r = top ? n2 : 0, J = top ? n2c : 0;
+                        const int I0 = i >> 1, I1 = I0 + (i & 1);
+                        u[(size_t)r * nx + i] += 0.5 * (uc[(size_t)J * ncx + I0] + uc[(size_t)J * ncx + I1]);
+                    }
+                }
+                return;
+            }
         }
     } else {
         j = color + 2 * xcd_line();
@@ -296,17 +319,40 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     double* b = a + L;
     double* c = b + L;
     double* d = c + L;
+    double* nb = d + L;     // rows j - 1 and j + 1 with the correction, [2][nx]
     const int nx = n1 + 1;
     const ST st(D);
     const gptr<double> u = gbl(D.u);
     const gptr<const double> f = gbl(static_cast<const double*>(D.f));
+    const bool pro = cl != nullptr && cl[blockIdx.y].n1 != 0;
+    if (pro) {
+        const MGDesc& C = cl[blockIdx.y];
+        const int ncx = C.n1 + 1;
+        const gptr<const double> uc = gbl(static_cast<const double*>(C.u));
+        for (int t = threadIdx.x; t < 2 * nx; t += NT) {
+            const int r = t < nx ? j - 1 : j + 1, i = t < nx ? t : t - nx;
+            double v = 0.0;
+            if (r >= 0 && r <= n2) {
+                const int J0 = r >> 1, J1 = J0 + (r & 1), I0 = i >> 1, I1 = I0 + (i & 1);
+                v = u[(size_t)r * nx + i] + 0.25 * (uc[(size_t)J0 * ncx + I0] + uc[(size_t)J0 * ncx + I1] +
+                                                    uc[(size_t)J1 * ncx + I0] + uc[(size_t)J1 * ncx + I1]);
+            }
+            nb[t] = v;
+        }
+        __syncthreads();
+    }
     for (int k = threadIdx.x; k < L; k += NT) {
         const int i = k + 1;
         const size_t o = (size_t)j * nx + i;
         const Coef q = st.at(j, i, o);
         double rhs = f[o];
-        if (j > 0) rhs -= q.S * u[o - nx] + q.SW * u[o - nx - 1] + q.SE * u[o - nx + 1];
-        if (j < n2) rhs -= q.N * u[o + nx] + q.NW * u[o + nx - 1] + q.NE * u[o + nx + 1];
+        if (pro) {
+            if (j > 0) rhs -= q.S * nb[i] + q.SW * nb[i - 1] + q.SE * nb[i + 1];
+            if (j < n2) rhs -= q.N * nb[nx + i] + q.NW * nb[nx + i - 1] + q.NE * nb[nx + i + 1];
+        } else {
+            if (j > 0) rhs -= q.S * u[o - nx] + q.SW * u[o - nx - 1] + q.SE * u[o - nx + 1];
+            if (j < n2) rhs -= q.N * u[o + nx] + q.NW * u[o + nx - 1] + q.NE * u[o + nx + 1];
+        }
         if (j == 0) rhs -= q.nn * u[o + 2 * nx];
         if (j == n2) rhs -= q.ss * u[o - 2 * nx];
         double aa = q.W, cc = q.E;
@@ -768,14 +814,21 @@ static int pcr_k(int total, int nt) {
     return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8;
 }
 
+// LDS of an x1-line workgroup: the tridiagonal system, plus the two prolonged
+// neighbour rows when it applies the coarse-grid correction
+static size_t x1_lds(int mn1, bool prolong) {
+    return sizeof(double) * (4 * (size_t)(mn1 - 1) + (prolong ? 2 * (size_t)(mn1 + 1) : 0));
+}
+
 template <int K, int NT, class ST>
-static void relax_x1_launch(apic_ctx* ctx, int l, int color) {
+static void relax_x1_launch(apic_ctx* ctx, int l, int color, bool prolong) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
-    const size_t lds = 4 * sizeof(double) * (size_t)(mn1 - 1);
+    const size_t lds = x1_lds(mn1, prolong);
     const int lines = color == 2 ? 2 : (mn2 + 1 - color + 1) / 2;
     const int G = (int)ctx->grains.size();
     hipLaunchKernelGGL((k_relax_x1<K, NT, ST>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
-                       ctx->mgdesc + (size_t)l * G, ctx->mgs, color);
+                       ctx->mgdesc + (size_t)l * G, ctx->mgs, color,
+                       prolong ? ctx->mgdesc + (size_t)(l + 1) * G : (const MGDesc*)nullptr);
 }
 
 template <int K, int LPB, int NT, class ST>
@@ -791,12 +844,12 @@ static void relax_x2_launch(apic_ctx* ctx, int l, int color) {
 }
 
 template <int NT, class ST>
-static void relax_x1_k(apic_ctx* ctx, int l, int color) {
+static void relax_x1_k(apic_ctx* ctx, int l, int color, bool prolong) {
     switch (pcr_k(ctx->lvl_max_n1[l] - 1, NT)) {
-        case 1: relax_x1_launch<1, NT, ST>(ctx, l, color); break;
-        case 2: relax_x1_launch<2, NT, ST>(ctx, l, color); break;
-        case 4: relax_x1_launch<4, NT, ST>(ctx, l, color); break;
-        default: relax_x1_launch<8, NT, ST>(ctx, l, color); break;
+        case 1: relax_x1_launch<1, NT, ST>(ctx, l, color, prolong); break;
+        case 2: relax_x1_launch<2, NT, ST>(ctx, l, color, prolong); break;
+        case 4: relax_x1_launch<4, NT, ST>(ctx, l, color, prolong); break;
+        default: relax_x1_launch<8, NT, ST>(ctx, l, color, prolong); break;
     }
 }
 
@@ -811,13 +864,24 @@ static void relax_x2_k(apic_ctx* ctx, int l, int color) {
 }
 
 // Both colours of the x1-line sweep of level l (on the finest level, then the
-// two axis rows).
+// two axis rows); with prolong, the first colour also applies the coarse-grid
+// correction from level l + 1.
 template <class ST>
-static void sweep_x1(apic_ctx* ctx, int l) {
+static void sweep_x1(apic_ctx* ctx, int l, bool prolong) {
     const int colors = std::is_same<ST, FineStencil>::value ? 3 : 2;
+    if (prolong && x1_lds(ctx->lvl_max_n1[l], true) > 65536) {
+        // rows too long to stage two more of them: the correction separately
+        const int G = (int)ctx->grains.size();
+        const int fn = ctx->lvl_max_nodes[l];
+        hipLaunchKernelGGL(k_prolong_add, dim3((fn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
+                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
+                           ctx->mgs);
+        prolong = false;
+    }
     for (int color = 0; color < colors; ++color) {
-        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<512, ST>(ctx, l, color);
-        else relax_x1_k<256, ST>(ctx, l, color);
+        const bool pro = prolong && color == 0;
+        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<512, ST>(ctx, l, color, pro);
+        else relax_x1_k<256, ST>(ctx, l, color, pro);
     }
 }
 
@@ -878,9 +942,9 @@ struct RelaxX2T {
 // level is large), the coarse ones are stored.
 template <class ST>
 static void smooth_st(apic_ctx* ctx, int l) {
-    sweep_x1<ST>(ctx, l);
+    sweep_x1<ST>(ctx, l, true);
     sweep_x2<ST>(ctx, l);
-    sweep_x1<ST>(ctx, l);
+    sweep_x1<ST>(ctx, l, false);
 }
 
 static void smooth(apic_ctx* ctx, int l) {
@@ -892,11 +956,11 @@ static void smooth(apic_ctx* ctx, int l) {
         smooth_st<FineStencil>(ctx, 0);
         return;
     }
-    sweep_x1<FineStencil>(ctx, 0);
+    sweep_x1<FineStencil>(ctx, 0, true);
     transpose<0>(ctx);
     for (int color = 0; color < 2; ++color) with_tri_shape<RelaxX2T>(ctx->lvl_max_n2[0] + 1, ctx, color);
     transpose<1>(ctx);
-    sweep_x1<FineStencil>(ctx, 0);
+    sweep_x1<FineStencil>(ctx, 0, false);
 }
 
 static void coarse_solve(apic_ctx* ctx, int l) {
@@ -960,13 +1024,7 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
                                ctx->mgdesc + (size_t)(l + 1) * G, ctx->mgs);
         coarse_solve(ctx, l + 1);
     }
-    for (int l = nl - 2; l >= 0; --l) {
-        const int fn = ctx->lvl_max_nodes[l];
-        hipLaunchKernelGGL(k_prolong_add, dim3((fn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
-                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G,
-                           ctx->mgs);
-        smooth(ctx, l);
-    }
+    for (int l = nl - 2; l >= 0; --l) smooth(ctx, l);   // correction applied by the first sweep
     residual_check(ctx, tol, 1, false);
     return hipGetLastError();
 }
