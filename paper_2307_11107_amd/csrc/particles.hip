@@ -23,6 +23,12 @@
 //   FP64 plain  -- double x1, x2 and velocities: 40 bytes per particle.
 // Dead slots: packed cell < 0 (FP32) or x1 > 0 (FP64); they are removed by the
 // periodic counting sort.
+// Multiply-adds are fused only within one source expression, never across
+// statements: the push loop inlines the particle update twice (two particles
+// per iteration), and both copies must round alike so that a particle's
+// trajectory does not depend on the slot it occupies.
+#pragma clang fp contract(on)
+
 #include "apic_internal.h"
 #include "device_common.h"
 
@@ -154,6 +160,7 @@ __device__ inline SplitConsts split_consts(const GrainParams& gp, const SpeciesP
 struct SplitState {
     int32_t c;
     float f1, f2, vR, vZ, vT;
+    unsigned long long g[4];   // push: the float2 nodal gradients of the cell, bit patterns
 };
 
 // Slot p of a 4-byte particle array, addressed as the array base plus a
@@ -184,8 +191,7 @@ __device__ inline bool is_dead(const SplitState& q) { return q.c < 0; }
 // Advances one particle given its loaded state q; writes slot p of b.
 __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams& sp,
                                      const SplitConsts& K, int s, int ns, int64_t p,
-                                     const SplitState& q, const PBuf& b,
-                                     const float2* __restrict__ grad, double* __restrict__ tally,
+                                     const SplitState& q, const PBuf& b, double* __restrict__ tally,
                                      unsigned long long* __restrict__ tally_count, int& i1n,
                                      int& i2n, float& f1n, float& f2n) {
     const int32_t c = q.c;
@@ -197,13 +203,10 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
     const float f1 = q.f1, f2 = q.f2;
     float vR = q.vR, vZ = q.vZ, vT = q.vT;
 
-    // gather (bilinear in the logical coordinates)
-    const int idx = i2 * nx + i1;
-    // float2 nodes read as 64-bit words (the vector type cannot be copied out
-    // of an explicitly global reference)
-    const gptr<const unsigned long long> gr = gbl(reinterpret_cast<const unsigned long long*>(grad));
-    const float2 g00 = __builtin_bit_cast(float2, gr[idx]), g10 = __builtin_bit_cast(float2, gr[idx + 1]);
-    const float2 g01 = __builtin_bit_cast(float2, gr[idx + nx]), g11 = __builtin_bit_cast(float2, gr[idx + nx + 1]);
+    // gather (bilinear in the logical coordinates); the cell's nodal gradients
+    // were loaded with the particle's state
+    const float2 g00 = __builtin_bit_cast(float2, q.g[0]), g10 = __builtin_bit_cast(float2, q.g[1]);
+    const float2 g01 = __builtin_bit_cast(float2, q.g[2]), g11 = __builtin_bit_cast(float2, q.g[3]);
     const float e1 = 1.f - f1, e2 = 1.f - f2;
     const float w00 = e1 * e2, w10 = f1 * e2, w01 = e1 * f2, w11 = f1 * f2;
     const float p1 = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
@@ -465,15 +468,13 @@ template <> struct PushTraits<true> {
     using S = SplitState;
     using T = float;
     using A = unsigned long long;   // two 32-bit fixed-point sums per LDS word
-    static constexpr int PB = 8;    // particles per thread and chunk
-    static constexpr int AHEAD = 1; // look-ahead of the state loads (particles)
+    static constexpr int PB = 8;    // particles per thread and chunk (even)
 };
 template <> struct PushTraits<false> {
     using S = PlainState;
     using T = double;
     using A = double;
     static constexpr int PB = 4;
-    static constexpr int AHEAD = 2;
 };
 
 constexpr int WIN_CAP = 4096;
@@ -772,9 +773,10 @@ __device__ inline void flush_counts(DevCounters* ctr, int s, uint32_t& n_live, u
 
 // Loading a chunk: the keys (packed cell / FP64 position) of all its particles
 // first -- the deposit window needs them before anything else -- then the rest
-// of each particle's state one particle (plus AHEAD look-ahead) at a time
-// inside a rolled loop, which keeps the loads in flight per wave close to what
-// the HBM pipe needs without inflating the register count.
+// of each particle's state (and, FP32, its cell's nodal gradients) one
+// particle ahead inside a rolled loop of two particles per iteration, which
+// keeps the loads in flight per wave close to what the HBM pipe needs without
+// inflating the register count.
 
 struct SplitKey { int32_t c; };
 struct PlainKey { double x1, x2; };
@@ -823,6 +825,21 @@ __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainSta
 }
 
 __device__ inline void set_key(SplitState& q, const SplitKey& k) { q.c = k.c; }
+
+// The four float2 nodal gradients around the particle's cell, read as 64-bit
+// words (the vector type cannot be copied out of an explicitly global
+// reference); issued together with the state loads, one particle ahead, so the
+// gather's latency overlaps the previous particle's work.
+__device__ inline void load_gather(const void* grad, int nx, const SplitKey& k, SplitState& q) {
+    if (k.c < 0) return;
+    const int idx = cell_i2(k.c) * nx + cell_i1(k.c);
+    const gptr<const unsigned long long> gr = gbl(static_cast<const unsigned long long*>(grad));
+    q.g[0] = gr[idx];
+    q.g[1] = gr[idx + 1];
+    q.g[2] = gr[idx + nx];
+    q.g[3] = gr[idx + nx + 1];
+}
+__device__ inline void load_gather(const void*, int, const PlainKey&, PlainState&) {}
 __device__ inline void set_key(PlainState& q, const PlainKey& k) {
     q.x1 = k.x1;
     q.x2 = k.x2;
@@ -854,7 +871,6 @@ template <bool SPLIT>
 __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix,
                                             int ntasks, int deposit) {
     using Tr = PushTraits<SPLIT>;
-    constexpr int PUSH_AHEAD = Tr::AHEAD;
     using S = typename Tr::S;
     using T = typename Tr::T;
     using A = typename Tr::A;
@@ -883,38 +899,45 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
         Key key[PB];
 #pragma unroll
         for (int k = 0; k < PB; ++k) load_key(v.b, base + k * BLOCK, v.n, key[k]);
-        // the first particles' states load while the window is reduced
-        S ahead[PUSH_AHEAD + 1];
-#pragma unroll
-        for (int a = 0; a < PUSH_AHEAD; ++a) load_fields(v.b, base + a * BLOCK, v.n, ahead[a]);
+        // the first particle's state loads while the window is reduced
+        S buf[2];
+        load_fields(v.b, base, v.n, buf[0]);
+        load_gather(v.grad, v.gp.nx, key[0], buf[0]);
         Window w;
         w.on = false;
         if (v.dep) w = keys_window(v.gp, key, red);
-#pragma unroll 1
-        for (int k = 0; k < PB; ++k) {
-            const int64_t p = base + k * BLOCK;
-            // the state PUSH_AHEAD particles ahead starts loading before this one is advanced
-            load_fields(v.b, p + PUSH_AHEAD * BLOCK, v.n, ahead[PUSH_AHEAD]);
-            S cur = ahead[0];
-            set_key(cur, key[0]);
-#pragma unroll
-            for (int a = 0; a < PUSH_AHEAD; ++a) ahead[a] = ahead[a + 1];
-#pragma unroll
-            for (int a = 0; a < PB - 1; ++a) key[a] = key[a + 1];
+        auto advance = [&](int64_t p, S cur, const Key& kk) {
+            set_key(cur, kk);
             int ia, ic;
             T f, g;
             int r;
             if constexpr (SPLIT)
-                r = push_split_one(v.gp, v.sp, K, v.s, v.ns, p, cur, v.b,
-                                   static_cast<const float2*>(v.grad), v.tally, v.tally_count, ia, ic, f, g);
+                r = push_split_one(v.gp, v.sp, K, v.s, v.ns, p, cur, v.b, v.tally, v.tally_count, ia, ic, f, g);
             else
                 r = push_plain_one(v.gp, v.sp, v.s, v.ns, p, cur, v.b,
                                    static_cast<const double2*>(v.grad), v.tally, v.tally_count, ia, ic, f, g);
-            if (r < 0) continue;
+            if (r < 0) return;
             ++n_live;
-            if (r == 1) { ++n_abs; continue; }
-            if (r == 2) { ++n_esc; continue; }
+            if (r == 1) { ++n_abs; return; }
+            if (r == 2) { ++n_esc; return; }
             if (w.on) deposit_one(v.gp, w, win, v.dep, ia, ic, f, g);
+        };
+        // two particles per iteration with two state buffers: each particle's
+        // state and gather load while the one before it is advanced, and no
+        // buffer is copied (a copy would wait for the loads it moves)
+#pragma unroll 1
+        for (int k = 0; k < PB; k += 2) {
+            const int64_t p = base + k * BLOCK;
+            load_fields(v.b, p + BLOCK, v.n, buf[1]);
+            load_gather(v.grad, v.gp.nx, key[1], buf[1]);
+            advance(p, buf[0], key[0]);
+            if (k + 2 < PB) {
+                load_fields(v.b, p + 2 * BLOCK, v.n, buf[0]);
+                load_gather(v.grad, v.gp.nx, key[2], buf[0]);
+            }
+            advance(p + BLOCK, buf[1], key[1]);
+#pragma unroll
+            for (int a = 0; a + 2 < PB; ++a) key[a] = key[a + 2];
         }
         if (w.on) {
             // the next chunk's window reduction synchronises before anything
