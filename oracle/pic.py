@@ -89,7 +89,10 @@ def _max_sampled(f, npts=4097):
 
 
 class Simulation:
-    def __init__(self, cfg):
+    def __init__(self, cfg, vacuum_field=True):
+        """vacuum_field=False leaves the potential unset (the caller sets it with
+        set_phi) and factorises the Poisson operator only when a solve is first
+        asked for: a large grid's factorisation takes minutes."""
         if not geo.check_alpha(cfg.alpha, cfg.x1_out):
             raise ValueError("need |alpha| < 1/4 and -1 < x1_out < 0")
         self.cfg = cfg
@@ -98,7 +101,7 @@ class Simulation:
         self.vol = gridmod.node_volumes(self.grid)
         self.V = float(np.sum(self.vol))
         self.A_out = gridmod.outer_area(self.grid)
-        self.solver = poisson.PoissonSolver(self.grid)
+        self._solver = None
         self.key = key_for(cfg.seed, cfg.grain)
         a = cfg.alpha
         self.M_vol = _max_sampled(lambda x2: geo.r_of(cfg.x1_out, x2, a) ** 3 - geo.r_of(-1.0, x2, a) ** 3)
@@ -126,8 +129,15 @@ class Simulation:
         self.escaped = np.zeros(ns, dtype=np.int64)
         self.F_el_sum = 0.0
         self.diag_steps = 0
-        self.phi = self.solver.solve(np.zeros(self.grid.shape), cfg.phi_grain, cfg.phi_out)
-        self.phi1, self.phi2 = field.nodal_gradient(self.phi, self.grid)
+        self.phi = self.phi1 = self.phi2 = None
+        if vacuum_field:
+            self.set_phi(self.solver.solve(np.zeros(self.grid.shape), cfg.phi_grain, cfg.phi_out))
+
+    @property
+    def solver(self):
+        if self._solver is None:
+            self._solver = poisson.PoissonSolver(self.grid)
+        return self._solver
 
     # ------------------------------------------------------------------ state
     @staticmethod

@@ -34,7 +34,9 @@ from . import geometry as geo
 
 def assemble(grid):
     """Sparse matrix of the discrete operator over all nodes (Dirichlet rows are
-    identity rows).  Unknown ordering: node (i1, i2) -> i2 (N1 + 1) + i1."""
+    identity rows).  Unknown ordering: node (i1, i2) -> i2 (N1 + 1) + i1.
+    The entries are formed for all rows of a kind at once (numpy arrays); a
+    node's coefficient from two terms (the centre) is their sum."""
     n1, n2 = grid.n1, grid.n2
     h1, h2 = grid.h1, grid.h2
     nx = n1 + 1
@@ -42,42 +44,43 @@ def assemble(grid):
     c11, c22, c12, c2 = geo.laplace_coeffs(X1, X2, grid.alpha)
     rows, cols, vals = [], [], []
 
-    def put(j, i, jj, ii, v):
-        rows.append(j * nx + i)
-        cols.append(jj * nx + ii)
-        vals.append(v)
+    def put(j, i, dj, di, v):
+        rows.append((j * nx + i).ravel())
+        cols.append(((j + dj) * nx + (i + di)).ravel())
+        vals.append(np.broadcast_to(v, j.shape).ravel())
 
-    for j in range(n2 + 1):
-        for i in range(n1 + 1):
-            if i == 0 or i == n1:
-                put(j, i, j, i, 1.0)
-                continue
-            a11 = c11[j, i] / (h1 * h1)
-            put(j, i, j, i - 1, a11)
-            put(j, i, j, i + 1, a11)
-            put(j, i, j, i, -2.0 * a11)
-            if j == 0 or j == n2:
-                # one-sided d/dx2 at the axis; d2/dx2^2 and mixed terms vanish
-                b = c2[j, i] / (2.0 * h2)
-                sgn = 1 if j == 0 else -1          # direction into the domain
-                # forward (j=0):  (-3 p0 + 4 p1 - p2) / (2 h2)
-                # backward (j=N): ( 3 pN - 4 pN-1 + pN-2) / (2 h2)
-                put(j, i, j, i, -3.0 * sgn * b)
-                put(j, i, j + sgn, i, 4.0 * sgn * b)
-                put(j, i, j + 2 * sgn, i, -1.0 * sgn * b)
-                continue
-            a22 = c22[j, i] / (h2 * h2)
-            b2 = c2[j, i] / (2.0 * h2)
-            a12 = c12[j, i] / (4.0 * h1 * h2)
-            put(j, i, j - 1, i, a22 - b2)
-            put(j, i, j + 1, i, a22 + b2)
-            put(j, i, j, i, -2.0 * a22)
-            put(j, i, j + 1, i + 1, a12)
-            put(j, i, j - 1, i - 1, a12)
-            put(j, i, j + 1, i - 1, -a12)
-            put(j, i, j - 1, i + 1, -a12)
+    # Dirichlet columns: identity rows
+    jd, idd = np.meshgrid(np.arange(n2 + 1), np.array([0, n1]), indexing="ij")
+    put(jd, idd, 0, 0, np.ones(jd.shape))
+    # every unknown row: d2/dx1^2
+    ju, iu = np.meshgrid(np.arange(n2 + 1), np.arange(1, n1), indexing="ij")
+    a11 = c11[ju, iu] / (h1 * h1)
+    put(ju, iu, 0, -1, a11)
+    put(ju, iu, 0, 1, a11)
+    put(ju, iu, 0, 0, -2.0 * a11)
+    # axis rows: one-sided d/dx2; d2/dx2^2 and mixed terms vanish
+    #   forward (j=0):  (-3 p0 + 4 p1 - p2) / (2 h2)
+    #   backward (j=N): ( 3 pN - 4 pN-1 + pN-2) / (2 h2)
+    for jj, sgn in ((0, 1), (n2, -1)):
+        ja, ia = np.meshgrid(np.array([jj]), np.arange(1, n1), indexing="ij")
+        b = c2[ja, ia] / (2.0 * h2)
+        put(ja, ia, 0, 0, -3.0 * sgn * b)
+        put(ja, ia, sgn, 0, 4.0 * sgn * b)
+        put(ja, ia, 2 * sgn, 0, -1.0 * sgn * b)
+    # interior rows
+    ji, ii = np.meshgrid(np.arange(1, n2), np.arange(1, n1), indexing="ij")
+    a22 = c22[ji, ii] / (h2 * h2)
+    b2 = c2[ji, ii] / (2.0 * h2)
+    a12 = c12[ji, ii] / (4.0 * h1 * h2)
+    put(ji, ii, -1, 0, a22 - b2)
+    put(ji, ii, 1, 0, a22 + b2)
+    put(ji, ii, 0, 0, -2.0 * a22)
+    put(ji, ii, 1, 1, a12)
+    put(ji, ii, -1, -1, a12)
+    put(ji, ii, 1, -1, -a12)
+    put(ji, ii, -1, 1, -a12)
     nn = (n1 + 1) * (n2 + 1)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(nn, nn))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nn, nn))
 
 
 class PoissonSolver:
