@@ -1181,12 +1181,37 @@ int apic_particles(apic_ctx* ctx, int32_t grain, int32_t species, int64_t cap, d
     if (e != hipSuccess) return fail(ctx, APIC_EDEVICE, std::string("apic_particles: ") + hipGetErrorString(e));
     *n_out = (int64_t)found;
     if ((int64_t)found > cap) return fail(ctx, APIC_EINVAL, "cap smaller than the particle count");
-    std::vector<size_t> order(found);
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return hid[a] < hid[b]; });
+    // order by id: ids are unique and dense (load indices, then the injection
+    // counter), so a placement table over [min, max] sorts in linear time; a
+    // sparse or repeated id range falls back to a comparison sort
+    std::vector<int64_t> order;
+    bool placed = false;
+    if (found > 0) {
+        const auto mm = std::minmax_element(hid.begin(), hid.begin() + (ptrdiff_t)found);
+        const int64_t lo = *mm.first, span = *mm.second - lo + 1;
+        if (span <= 4 * (int64_t)found + 1024) {
+            std::vector<int64_t> at((size_t)span, -1);
+            placed = true;
+            for (size_t k = 0; k < found && placed; ++k) {
+                int64_t& a = at[(size_t)(hid[k] - lo)];
+                if (a >= 0) placed = false;
+                a = (int64_t)k;
+            }
+            if (placed) {
+                order.reserve(found);
+                for (int64_t a : at)
+                    if (a >= 0) order.push_back(a);
+            }
+        }
+    }
+    if (!placed) {
+        order.resize(found);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return hid[a] < hid[b]; });
+    }
     double* dst[5] = {x1, x2, vR, vZ, vTheta};
     for (size_t k = 0; k < found; ++k) {
-        const size_t o = order[k];
+        const size_t o = (size_t)order[k];
         for (int c = 0; c < 5; ++c) dst[c][k] = hx[(size_t)c * m + o];
         if (id) id[k] = hid[o];
     }
