@@ -174,6 +174,13 @@ __device__ __forceinline__ gptr<T> slot4(T* base, int64_t p) {
     return (gptr<T>)((gptr<C>)gbl(reinterpret_cast<C*>(base)) + ((uint32_t)p << 2));
 }
 
+// The particle arrays stream through once per step: their loads and stores
+// are non-temporal, which keeps L2 for the field and the deposit.
+template <typename T>
+__device__ __forceinline__ T ld_stream(gptr<const T> a) { return __builtin_nontemporal_load(a); }
+template <typename T>
+__device__ __forceinline__ void st_stream(gptr<T> a, T v) { __builtin_nontemporal_store(v, a); }
+
 __device__ inline SplitState load_split(const PBuf& b, int64_t p) {
     SplitState q;
     q.c = *slot4(static_cast<const int32_t*>(b.pos0), p);
@@ -312,12 +319,12 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
         *cell = DEAD;
         return 2;
     }
-    *cell = pack_cell(i1n, i2n);
-    *slot4(static_cast<float*>(b.pos1), p) = f1n;
-    *slot4(static_cast<float*>(b.pos2), p) = f2n;
-    *slot4(static_cast<float*>(b.vR), p) = vRn;
-    *slot4(static_cast<float*>(b.vZ), p) = vZ;
-    *slot4(static_cast<float*>(b.vT), p) = vTn;
+    st_stream(cell, pack_cell(i1n, i2n));
+    st_stream(slot4(static_cast<float*>(b.pos1), p), f1n);
+    st_stream(slot4(static_cast<float*>(b.pos2), p), f2n);
+    st_stream(slot4(static_cast<float*>(b.vR), p), vRn);
+    st_stream(slot4(static_cast<float*>(b.vZ), p), vZ);
+    st_stream(slot4(static_cast<float*>(b.vT), p), vTn);
     return 0;
 }
 
@@ -782,7 +789,7 @@ struct SplitKey { int32_t c; };
 struct PlainKey { double x1, x2; };
 
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, SplitKey& k) {
-    k.c = p < n ? *slot4(static_cast<const int32_t*>(b.pos0), p) : DEAD;
+    k.c = p < n ? ld_stream(slot4(static_cast<const int32_t*>(b.pos0), p)) : DEAD;
 }
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, PlainKey& k) {
     if (p < n) {
@@ -811,11 +818,11 @@ __device__ inline bool key_cell(const GrainParams& gp, const PlainKey& k, int& i
 // need not wait for the key
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, SplitState& q) {
     if (p >= n) return;
-    q.f1 = *slot4(static_cast<const float*>(b.pos1), p);
-    q.f2 = *slot4(static_cast<const float*>(b.pos2), p);
-    q.vR = *slot4(static_cast<const float*>(b.vR), p);
-    q.vZ = *slot4(static_cast<const float*>(b.vZ), p);
-    q.vT = *slot4(static_cast<const float*>(b.vT), p);
+    q.f1 = ld_stream(slot4(static_cast<const float*>(b.pos1), p));
+    q.f2 = ld_stream(slot4(static_cast<const float*>(b.pos2), p));
+    q.vR = ld_stream(slot4(static_cast<const float*>(b.vR), p));
+    q.vZ = ld_stream(slot4(static_cast<const float*>(b.vZ), p));
+    q.vT = ld_stream(slot4(static_cast<const float*>(b.vT), p));
 }
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainState& q) {
     if (p >= n) return;
@@ -1336,20 +1343,78 @@ constexpr int SCAN_SEG = 4096;      // histogram entries per scan workgroup
 int max_sort_blocks() { return SORT_BLOCKS_MAX; }
 int scan_seg_len() { return SCAN_SEG; }
 
-__device__ inline int tile_key(const GrainParams& gp, bool split, const PBuf& b, int64_t p) {
-    int i1, i2;
-    if (split) {
-        const int32_t c = gbl(static_cast<const int32_t*>(b.pos0))[p];
-        if (c < 0) return -1;
-        i1 = cell_i1(c);
-        i2 = cell_i2(c);
-    } else {
-        const double x1 = gbl(static_cast<const double*>(b.pos1))[p];
-        if (x1 > 0.0) return -1;
-        double f1, f2;
-        locate64(gp, x1, gbl(static_cast<const double*>(b.pos2))[p], i1, i2, f1, f2);
-    }
+__device__ inline int tile_of(const GrainParams& gp, int i1, int i2) {
     return (i2 >> gp.tile_log2) * gp.ntx + (i1 >> gp.tile_log2);
+}
+
+// One particle's slot contents, moved as a unit by the scatter; its tile key
+// comes from the position words it already holds.
+template <bool SPLIT> struct Moved;
+template <> struct Moved<true> {
+    uint32_t w[7];      // cell, f1, f2, vR, vZ, vT, id
+};
+template <> struct Moved<false> {
+    uint64_t d[5];      // x1, x2, vR, vZ, vT bits
+    uint32_t id;
+};
+
+__device__ inline int tile_key(const GrainParams& gp, const Moved<true>& m) {
+    const int32_t c = (int32_t)m.w[0];
+    if (c < 0) return -1;
+    return tile_of(gp, cell_i1(c), cell_i2(c));
+}
+__device__ inline int tile_key(const GrainParams& gp, const Moved<false>& m) {
+    const double x1 = __builtin_bit_cast(double, m.d[0]);
+    if (x1 > 0.0) return -1;
+    int i1, i2;
+    double f1, f2;
+    locate64(gp, x1, __builtin_bit_cast(double, m.d[1]), i1, i2, f1, f2);
+    return tile_of(gp, i1, i2);
+}
+
+// the position words only (histogram pass)
+__device__ inline void load_pos(const PBuf& b, int64_t p, Moved<true>& m) {
+    m.w[0] = *slot4(static_cast<const uint32_t*>(b.pos0), p);
+}
+__device__ inline void load_pos(const PBuf& b, int64_t p, Moved<false>& m) {
+    m.d[0] = gbl(static_cast<const uint64_t*>(b.pos1))[p];
+    m.d[1] = gbl(static_cast<const uint64_t*>(b.pos2))[p];
+}
+
+__device__ inline void load_moved(const PBuf& b, int64_t p, Moved<true>& m) {
+    m.w[0] = *slot4(static_cast<const uint32_t*>(b.pos0), p);
+    m.w[1] = *slot4(static_cast<const uint32_t*>(b.pos1), p);
+    m.w[2] = *slot4(static_cast<const uint32_t*>(b.pos2), p);
+    m.w[3] = *slot4(static_cast<const uint32_t*>(b.vR), p);
+    m.w[4] = *slot4(static_cast<const uint32_t*>(b.vZ), p);
+    m.w[5] = *slot4(static_cast<const uint32_t*>(b.vT), p);
+    m.w[6] = *slot4(static_cast<const uint32_t*>(b.id), p);
+}
+__device__ inline void load_moved(const PBuf& b, int64_t p, Moved<false>& m) {
+    m.d[0] = gbl(static_cast<const uint64_t*>(b.pos1))[p];
+    m.d[1] = gbl(static_cast<const uint64_t*>(b.pos2))[p];
+    m.d[2] = gbl(static_cast<const uint64_t*>(b.vR))[p];
+    m.d[3] = gbl(static_cast<const uint64_t*>(b.vZ))[p];
+    m.d[4] = gbl(static_cast<const uint64_t*>(b.vT))[p];
+    m.id = gbl(b.id)[p];
+}
+
+__device__ inline void store_moved(const PBuf& b, int64_t o, const Moved<true>& m) {
+    *slot4(static_cast<uint32_t*>(b.pos0), o) = m.w[0];
+    *slot4(static_cast<uint32_t*>(b.pos1), o) = m.w[1];
+    *slot4(static_cast<uint32_t*>(b.pos2), o) = m.w[2];
+    *slot4(static_cast<uint32_t*>(b.vR), o) = m.w[3];
+    *slot4(static_cast<uint32_t*>(b.vZ), o) = m.w[4];
+    *slot4(static_cast<uint32_t*>(b.vT), o) = m.w[5];
+    *slot4(static_cast<uint32_t*>(b.id), o) = m.w[6];
+}
+__device__ inline void store_moved(const PBuf& b, int64_t o, const Moved<false>& m) {
+    gbl(static_cast<uint64_t*>(b.pos1))[o] = m.d[0];
+    gbl(static_cast<uint64_t*>(b.pos2))[o] = m.d[1];
+    gbl(static_cast<uint64_t*>(b.vR))[o] = m.d[2];
+    gbl(static_cast<uint64_t*>(b.vZ))[o] = m.d[3];
+    gbl(static_cast<uint64_t*>(b.vT))[o] = m.d[4];
+    gbl(b.id)[o] = m.id;
 }
 
 // Run-length segments of equal keys inside a wave (all 64 lanes active): the
@@ -1371,8 +1436,15 @@ __device__ inline void sort_range(int64_t n, int blocks, int64_t& lo, int64_t& h
     hi = min<int64_t>(lo + per, n);
 }
 
+// Batches of BLOCK slots per iteration of the histogram and scatter loops,
+// all their loads issued before the first is used, so a workgroup's slot range
+// streams with many loads in flight.
+constexpr int HIST_BATCHES = 8;
+constexpr int SCATTER_BATCHES = 8;
+
+template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_tile_hist(const PushTask* __restrict__ tasks, bool split) {
+k_tile_hist(const PushTask* __restrict__ tasks) {
     extern __shared__ int lh[];
     const PushTask& T = tasks[blockIdx.y];
     const int SB = T.sort_blocks;
@@ -1384,13 +1456,22 @@ k_tile_hist(const PushTask* __restrict__ tasks, bool split) {
     const PBuf b = T.buf[T.ctr->cur[T.s]];
     int64_t lo, hi;
     sort_range(T.ctr->n[T.s], SB, lo, hi);
-    for (int64_t base = lo; base < hi; base += BLOCK) {
-        const int64_t p = base + threadIdx.x;
-        const int key = p < hi ? tile_key(gp, split, b, p) : -1;
-        int head, len;
-        bool is_head;
-        wave_runs(key, head, len, is_head);
-        if (is_head && key >= 0) atomicAdd(&lh[key], len);
+    for (int64_t base = lo; base < hi; base += HIST_BATCHES * BLOCK) {
+        Moved<SPLIT> m[HIST_BATCHES];
+#pragma unroll
+        for (int k = 0; k < HIST_BATCHES; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            if (p < hi) load_pos(b, p, m[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < HIST_BATCHES; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            const int key = p < hi ? tile_key(gp, m[k]) : -1;
+            int head, len;
+            bool is_head;
+            wave_runs(key, head, len, is_head);
+            if (is_head && key >= 0) atomicAdd(&lh[key], len);
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nt; t += BLOCK) gbl(T.hist)[(size_t)t * SB + blockIdx.x] = lh[t];
@@ -1481,57 +1562,11 @@ k_scan_apply(const PushTask* __restrict__ tasks) {
     }
 }
 
-// One particle's slot contents, moved as a unit by the scatter.
-struct Moved {
-    uint32_t w[5];      // FP32: cell, f1, f2, vR, vZ bits; FP64: unused
-    uint32_t vT;
-    uint64_t d[5];      // FP64: x1, x2, vR, vZ, vT bits
-    uint32_t id;
-};
-
-__device__ inline void load_moved(bool split, const PBuf& b, int64_t p, Moved& m) {
-    if (split) {
-        m.w[0] = gbl(static_cast<const uint32_t*>(b.pos0))[p];
-        m.w[1] = gbl(static_cast<const uint32_t*>(b.pos1))[p];
-        m.w[2] = gbl(static_cast<const uint32_t*>(b.pos2))[p];
-        m.w[3] = gbl(static_cast<const uint32_t*>(b.vR))[p];
-        m.w[4] = gbl(static_cast<const uint32_t*>(b.vZ))[p];
-        m.vT = gbl(static_cast<const uint32_t*>(b.vT))[p];
-    } else {
-        m.d[0] = gbl(static_cast<const uint64_t*>(b.pos1))[p];
-        m.d[1] = gbl(static_cast<const uint64_t*>(b.pos2))[p];
-        m.d[2] = gbl(static_cast<const uint64_t*>(b.vR))[p];
-        m.d[3] = gbl(static_cast<const uint64_t*>(b.vZ))[p];
-        m.d[4] = gbl(static_cast<const uint64_t*>(b.vT))[p];
-    }
-    m.id = gbl(b.id)[p];
-}
-
-__device__ inline void store_moved(bool split, const PBuf& b, int64_t o, const Moved& m) {
-    if (split) {
-        gbl(static_cast<uint32_t*>(b.pos0))[o] = m.w[0];
-        gbl(static_cast<uint32_t*>(b.pos1))[o] = m.w[1];
-        gbl(static_cast<uint32_t*>(b.pos2))[o] = m.w[2];
-        gbl(static_cast<uint32_t*>(b.vR))[o] = m.w[3];
-        gbl(static_cast<uint32_t*>(b.vZ))[o] = m.w[4];
-        gbl(static_cast<uint32_t*>(b.vT))[o] = m.vT;
-    } else {
-        gbl(static_cast<uint64_t*>(b.pos1))[o] = m.d[0];
-        gbl(static_cast<uint64_t*>(b.pos2))[o] = m.d[1];
-        gbl(static_cast<uint64_t*>(b.vR))[o] = m.d[2];
-        gbl(static_cast<uint64_t*>(b.vZ))[o] = m.d[3];
-        gbl(static_cast<uint64_t*>(b.vT))[o] = m.d[4];
-    }
-    gbl(b.id)[o] = m.id;
-}
-
-// Scatter: SCATTER_BATCHES batches of BLOCK particles per iteration, all their
-// loads issued before the LDS cursor updates, so the slot range streams at
-// full memory parallelism.
-constexpr int SCATTER_BATCHES = 8;
-
+// Scatter: each wave's runs of equal tiles take their offsets with one LDS
+// atomic per run.
+template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
+k_tile_scatter(const PushTask* __restrict__ tasks) {
     extern __shared__ int cur[];
     const PushTask& T = tasks[blockIdx.y];
     const int SB = T.sort_blocks;
@@ -1547,23 +1582,23 @@ k_tile_scatter(const PushTask* __restrict__ tasks, bool split) {
     int64_t lo, hi;
     sort_range(T.ctr->n[T.s], SB, lo, hi);
     for (int64_t base = lo; base < hi; base += SCATTER_BATCHES * BLOCK) {
-        Moved m[SCATTER_BATCHES];
-        int key[SCATTER_BATCHES];
+        Moved<SPLIT> m[SCATTER_BATCHES];
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
             const int64_t p = base + k * BLOCK + threadIdx.x;
-            key[k] = p < hi ? tile_key(gp, split, src, p) : -1;
-            if (p < hi) load_moved(split, src, p, m[k]);
+            if (p < hi) load_moved(src, p, m[k]);
         }
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
+            const int64_t p = base + k * BLOCK + threadIdx.x;
+            const int key = p < hi ? tile_key(gp, m[k]) : -1;
             int head, len;
             bool is_head;
-            wave_runs(key[k], head, len, is_head);
+            wave_runs(key, head, len, is_head);
             int start = 0;
-            if (is_head && key[k] >= 0) start = atomicAdd(&cur[key[k]], len);
+            if (is_head && key >= 0) start = atomicAdd(&cur[key], len);
             const int64_t o = (int64_t)__shfl(start, head) + (lane - head);
-            if (key[k] >= 0) store_moved(split, dst, o, m[k]);
+            if (key >= 0) store_moved(dst, o, m[k]);
         }
     }
 }
@@ -1665,11 +1700,13 @@ hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks) {
     const PushTask* t = ctx->tasks + first_task;
     const dim3 sgrid(ctx->max_sort_blocks, n_tasks);
     const dim3 cgrid(ctx->max_segs, n_tasks);
-    hipLaunchKernelGGL(k_tile_hist, sgrid, dim3(BLOCK), lds, ctx->stream, t, split);
+    if (split) hipLaunchKernelGGL(k_tile_hist<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
+    else hipLaunchKernelGGL(k_tile_hist<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
     hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, t);
     hipLaunchKernelGGL(k_scan_segs, dim3(n_tasks), dim3(1024), 0, ctx->stream, t);
     hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, t);
-    hipLaunchKernelGGL(k_tile_scatter, sgrid, dim3(BLOCK), lds, ctx->stream, t, split);
+    if (split) hipLaunchKernelGGL(k_tile_scatter<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
+    else hipLaunchKernelGGL(k_tile_scatter<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
     hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, t, n_tasks);
     return hipGetLastError();
 }
