@@ -85,7 +85,10 @@ typedef struct {
     int32_t precision;          /* APIC_FP32_SPLIT (cell index + FP32 offset) or APIC_FP64 */
     int32_t inject;             /* 1: Maxwellian flux injection every step                 */
     int32_t frozen_field;       /* 1: phi stays as last set (no deposit, no solve)         */
-    int32_t sort_every;         /* re-sort particles by cell every k steps (0: 8)          */
+    int32_t sort_every;         /* re-sort particles by cell every k steps (0: 4); a
+                                   species 2^l times slower (thermal speed) than its
+                                   grain's fastest is re-sorted every k 2^l steps,
+                                   2^l <= 16                                               */
     double poisson_tol;         /* in-step solves: stop at |r| <= tol |b| (0: 1e-10)       */
     int32_t poisson_max_cycles; /* in-step multigrid cycle cap (0: 40)                     */
     int32_t autotune;           /* 1: the first steps choose the launch schedule (below)   */

@@ -536,6 +536,8 @@ void fill_tasks(apic_ctx* ctx) {
     ctx->max_segs = 1;
     for (size_t gi = 0; gi < ctx->grains.size(); ++gi) {
         Grain& g = ctx->grains[gi];
+        double sig_max = 0.0;
+        for (int s = 0; s < g.ns; ++s) sig_max = std::max(sig_max, g.sp[s].sigma);
         for (int s = 0; s < g.ns; ++s) {
             PushTask t;
             std::memset(&t, 0, sizeof(t));
@@ -557,6 +559,12 @@ void fill_tasks(apic_ctx* ctx) {
             t.ns = g.ns;
             t.grain = (int)gi;
             t.sort_blocks = g.sort_blocks[s];
+            // a species k times slower (thermal speed) than the grain's fastest
+            // drifts out of its tiles k times later: sorted every
+            // sort_every * 2^level steps, 2^level <= k, at most 16x apart
+            t.sort_level = 0;
+            while (t.sort_level + 1 < SORT_LEVELS && g.sp[s].sigma * (2 << t.sort_level) <= sig_max)
+                ++t.sort_level;
             // a step injects at most floor(inj_inc / 2^32) + 1 particles; the
             // tasks' injection workgroups are laid end to end
             t.inj_block0 = ctx->inj_blocks;
@@ -700,10 +708,11 @@ int apply_tiles(apic_ctx* ctx, int t) {
     return upload_tasks(ctx);
 }
 
-int sort_all(apic_ctx* ctx) {
-    TRY(run_phase(ctx, G_SORT, [&] { (void)launch_sort(ctx, 0, ctx->ntasks); }));
-    for (auto& g : ctx->grains)
-        for (int s = 0; s < g.ns; ++s) g.cur[s] = 1 - g.cur[s];
+// Sort of the tasks whose sort level is at most `level` (all by default).
+int sort_all(apic_ctx* ctx, int level = SORT_LEVELS - 1) {
+    TRY(run_phase(ctx, G_SORT + level, [&] { (void)launch_sort(ctx, 0, ctx->ntasks, level); }));
+    for (const PushTask& t : ctx->tasks_h)
+        if (t.sort_level <= level) ctx->grains[t.grain].cur[t.s] ^= 1;
     return APIC_OK;
 }
 
@@ -736,7 +745,7 @@ int sort_every(const apic_ctx* ctx) {
 // The sort of a step runs on the side stream, overlapped with the field solve
 // of the same step (the solve needs only the deposit, the sort only the
 // particles); the main stream waits for it at the end of the step.
-int sort_all_async(apic_ctx* ctx) {
+int sort_all_async(apic_ctx* ctx, int level) {
     HIPCHK(ctx, hipEventRecord(ctx->ev_fork, ctx->stream));
     HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     hipStream_t main = ctx->stream;
@@ -744,7 +753,7 @@ int sort_all_async(apic_ctx* ctx) {
     int rc;
     {
         Timer t(ctx, 2);
-        rc = sort_all(ctx);
+        rc = sort_all(ctx, level);
     }
     ctx->stream = main;
     TRY(rc);
@@ -771,8 +780,14 @@ int do_step(apic_ctx* ctx) {
         TRY(run_phase(ctx, G_INJ, [&] { (void)launch_inject(ctx, !frozen); }));
     }
     const uint64_t step = ctx->grains[0].step_index + 1;
-    const bool sort_now = step % (uint64_t)sort_every(ctx) == 0;
-    if (sort_now) TRY(sort_all_async(ctx));
+    const uint64_t se = (uint64_t)sort_every(ctx);
+    const bool sort_now = step % se == 0;
+    if (sort_now) {
+        // sort level: the tasks due at this multiple of sort_every
+        int level = 0;
+        for (uint64_t k = step / se; level + 1 < SORT_LEVELS && (k & 1) == 0; k >>= 1) ++level;
+        TRY(sort_all_async(ctx, level));
+    }
     {
         Timer t(ctx, 3);
         if (!frozen) {
@@ -883,11 +898,20 @@ int autotune(apic_ctx* ctx, int64_t* left) {
             TRY(timed(ctx, clk, [&] { return push_phase(ctx); }, &ms));
             st->push_after.push_back(ms);
             if (++st->idx == 16) {
+                // the slower species are sorted 2^level times less often:
+                // the sort's cost per interval is the share of the particles
+                // sorted at every one of them
+                double all = 0.0, due = 0.0;
+                for (const PushTask& t : ctx->tasks_h) {
+                    all += (double)t.capacity;
+                    due += (double)t.capacity / (double)(1 << t.sort_level);
+                }
+                const double sort_share = all > 0.0 ? due / all : 1.0;
                 double best = 1e30, sum = 0;
                 int k_best = 8;
                 for (int k = 1; k <= 16; ++k) {
                     sum += st->push_after[k - 1];
-                    const double per = (st->sort_ms + sum) / k;
+                    const double per = (st->sort_ms * sort_share + sum) / k;
                     if (per < best) {
                         best = per;
                         k_best = k;

@@ -97,6 +97,7 @@ struct PushTask {
     uint64_t inj_inc;           // particles injected per step, 2^-32 units
     int s, ns, grain, sort_blocks;
     int inj_block0;             // first workgroup of this task in the injection launch
+    int sort_level;             // sorted every (sort_every << sort_level) steps
 };
 
 // One grain, as the field kernels see it.
@@ -196,7 +197,7 @@ struct Schedule {
     int push_wg_per_cu = 8;     // persistent push workgroups per compute unit (capped at
                                 // what stays resident)
     int tile_log2 = 4;          // sort tile edge, log2 cells (capped per grain)
-    int sort_every = 8;         // steps between sorts
+    int sort_every = 4;         // steps between sorts
 };
 
 // Progress of the autotuner across apic_step calls.
@@ -210,7 +211,8 @@ struct TuneState {
 
 struct TimerPair { hipEvent_t a, b; int kind; };
 
-enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_SORT, G_COUNT };
+constexpr int SORT_LEVELS = 5;   // a slow species is sorted up to 16x less often
+enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_SORT, G_COUNT = G_SORT + SORT_LEVELS };
 
 }  // namespace apic
 
@@ -251,7 +253,7 @@ struct apic_ctx {
     bool tuned = false;
     bool tuning = false;                    // launches run eagerly while tuning
     apic::TuneState tune;
-    hipGraphExec_t graph[apic::G_COUNT] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t graph[apic::G_COUNT] = {};
     // profiling
     bool profiling = false;
     std::vector<apic::TimerPair> timers;   // recorded, not yet harvested
@@ -267,7 +269,7 @@ namespace apic {
 hipError_t launch_push(apic_ctx* ctx, bool deposit);
 hipError_t launch_deposit(apic_ctx* ctx);
 hipError_t launch_inject(apic_ctx* ctx, bool deposit);
-hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks);
+hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks, int max_level = SORT_LEVELS);
 hipError_t launch_load(apic_ctx* ctx, Grain& g, int s, int64_t n);
 hipError_t launch_set_particles(apic_ctx* ctx, Grain& g, int s, int64_t n, const double* dx1,
                                 const double* dx2, const double* dvR, const double* dvZ,

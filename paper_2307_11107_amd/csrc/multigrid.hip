@@ -758,10 +758,13 @@ k_prolong_add(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse
 // unknowns and rhs = u on the Dirichlet columns (identity rows of A), so the
 // same kernel serves a correction level (u = 0 there) and a grid that is
 // itself small enough.  The workgroup stages rhs in LDS once; each wave then
-// streams rows of the inverse (rows padded to an even length, read two
-// entries per lane and load).  The kernel writes u only on unknown rows and
-// reads it only on Dirichlet columns.
-constexpr int CS_ROWS = 8;   // rows per workgroup
+// streams CS_RW rows of the inverse together (rows padded to an even length,
+// two entries per lane and load), so every rhs pair read from LDS serves
+// CS_RW rows and CS_RW loads are in flight per step.  The kernel writes u only
+// on unknown rows and reads it only on Dirichlet columns.
+constexpr int CS_RW = 4;                          // rows per wave
+constexpr int CS_ROWS = CS_RW * (MG_BLOCK / 64);  // rows per workgroup
+constexpr int CS_STAGE = 8;
 
 __global__ void __launch_bounds__(MG_BLOCK)
 k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
@@ -774,31 +777,56 @@ k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
     if (row0 >= m) return;
     const gptr<double> u = gbl(D.u);
     const gptr<const double> f = gbl(static_cast<const double*>(D.f));
-    for (int k = threadIdx.x; k < mp; k += MG_BLOCK) {
-        double v = 0.0;
-        if (k < m) {
-            const int i = k % nx;
-            v = (i == 0 || i == D.n1) ? u[k] : f[k];
+    // staged in batches of CS_STAGE independent loads per thread (a loop of
+    // one load and one LDS store per trip would wait out every load in turn)
+    for (int k0 = threadIdx.x; k0 < mp; k0 += CS_STAGE * MG_BLOCK) {
+        double v[CS_STAGE];
+#pragma unroll
+        for (int j = 0; j < CS_STAGE; ++j) {
+            const int k = k0 + j * MG_BLOCK;
+            v[j] = 0.0;
+            if (k < m) {
+                const int i = k % nx;
+                v[j] = (i == 0 || i == D.n1) ? u[k] : f[k];
+            }
         }
-        rhs[k] = v;
+#pragma unroll
+        for (int j = 0; j < CS_STAGE; ++j)
+            if (k0 + j * MG_BLOCK < mp) rhs[k0 + j * MG_BLOCK] = v[j];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    for (int r = threadIdx.x >> 6; r < CS_ROWS; r += MG_BLOCK / 64) {
-        const int row = row0 + r;
-        if (row >= m) break;
-        const int ri = row % nx;
-        if (ri == 0 || ri == D.n1) continue;
-        const gptr<const dbl2> a = (gptr<const dbl2>)gbl(D.inv + (size_t)row * mp);
-        double acc = 0.0;
-#pragma unroll 4
-        for (int k = lane; k < mp / 2; k += 64) {
-            const dbl2 v = a[k];
-            acc += v.x * rhs[2 * k] + v.y * rhs[2 * k + 1];
-        }
+    const int rw = row0 + (threadIdx.x >> 6) * CS_RW;
+    if (rw >= m) return;
+    // rows past the end repeat the last row (loaded, never stored)
+    gptr<const dbl2> a[CS_RW];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) u[row] = acc;
+    for (int r = 0; r < CS_RW; ++r) a[r] = (gptr<const dbl2>)gbl(D.inv + (size_t)min(rw + r, m - 1) * mp);
+    const dbl2* x = reinterpret_cast<const dbl2*>(rhs);
+    double acc[CS_RW];
+#pragma unroll
+    for (int r = 0; r < CS_RW; ++r) acc[r] = 0.0;
+#pragma unroll 2
+    for (int k = lane; k < mp / 2; k += 64) {
+        const dbl2 xv = x[k];
+#pragma unroll
+        for (int r = 0; r < CS_RW; ++r) {
+            const dbl2 v = a[r][k];
+            acc[r] += v.x * xv.x + v.y * xv.y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < CS_RW; ++r) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < CS_RW; ++r) {
+            const int row = rw + r;
+            const int ri = row % nx;
+            if (row < m && ri != 0 && ri != D.n1) u[row] = acc[r];
+        }
     }
 }
 

@@ -1444,11 +1444,11 @@ constexpr int SCATTER_BATCHES = 8;
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_tile_hist(const PushTask* __restrict__ tasks) {
+k_tile_hist(const PushTask* __restrict__ tasks, int max_level) {
     extern __shared__ int lh[];
     const PushTask& T = tasks[blockIdx.y];
     const int SB = T.sort_blocks;
-    if ((int)blockIdx.x >= SB) return;
+    if ((int)blockIdx.x >= SB || T.sort_level > max_level) return;
     const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
     for (int t = threadIdx.x; t < nt; t += BLOCK) lh[t] = 0;
@@ -1502,8 +1502,9 @@ __device__ inline int block_scan_excl(int v, int* tmp, int& total) {
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_scan_reduce(const PushTask* __restrict__ tasks) {
+k_scan_reduce(const PushTask* __restrict__ tasks, int max_level) {
     const PushTask& T = tasks[blockIdx.y];
+    if (T.sort_level > max_level) return;
     const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
     const int64_t lo = (int64_t)blockIdx.x * SCAN_SEG;
     if (lo >= len) return;
@@ -1517,8 +1518,9 @@ k_scan_reduce(const PushTask* __restrict__ tasks) {
 }
 
 __global__ void __launch_bounds__(1024)
-k_scan_segs(const PushTask* __restrict__ tasks) {
+k_scan_segs(const PushTask* __restrict__ tasks, int max_level) {
     const PushTask& T = tasks[blockIdx.x];
+    if (T.sort_level > max_level) return;
     const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
     const int nseg = (int)((len + SCAN_SEG - 1) / SCAN_SEG);
     __shared__ int tmp[1024 / 64];
@@ -1538,8 +1540,9 @@ k_scan_segs(const PushTask* __restrict__ tasks) {
 }
 
 __global__ void __launch_bounds__(BLOCK)
-k_scan_apply(const PushTask* __restrict__ tasks) {
+k_scan_apply(const PushTask* __restrict__ tasks, int max_level) {
     const PushTask& T = tasks[blockIdx.y];
+    if (T.sort_level > max_level) return;
     const int64_t len = (int64_t)T.gp.ntiles * T.sort_blocks;
     const int64_t lo = (int64_t)blockIdx.x * SCAN_SEG;
     if (lo >= len) return;
@@ -1566,11 +1569,11 @@ k_scan_apply(const PushTask* __restrict__ tasks) {
 // atomic per run.
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
-k_tile_scatter(const PushTask* __restrict__ tasks) {
+k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
     extern __shared__ int cur[];
     const PushTask& T = tasks[blockIdx.y];
     const int SB = T.sort_blocks;
-    if ((int)blockIdx.x >= SB) return;
+    if ((int)blockIdx.x >= SB || T.sort_level > max_level) return;
     const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
     for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = gbl(T.hist_off)[(size_t)t * SB + blockIdx.x];
@@ -1605,8 +1608,9 @@ k_tile_scatter(const PushTask* __restrict__ tasks) {
 
 // the sorted buffer becomes the current one; slots = live particles
 __global__ void __launch_bounds__(BLOCK)
-k_sort_commit(const PushTask* __restrict__ tasks, int ntasks) {
+k_sort_commit(const PushTask* __restrict__ tasks, int ntasks, int max_level) {
     for (int t = threadIdx.x; t < ntasks; t += BLOCK) {
+        if (tasks[t].sort_level > max_level) continue;
         DevCounters* ctr = tasks[t].ctr;
         const int s = tasks[t].s;
         ctr->n[s] = ctr->n_sorted[s];
@@ -1694,20 +1698,20 @@ hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
     return hipGetLastError();
 }
 
-hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks) {
+hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks, int max_level) {
     const bool split = is_split(ctx);
     const size_t lds = sizeof(int) * (size_t)ctx->max_ntiles;
     const PushTask* t = ctx->tasks + first_task;
     const dim3 sgrid(ctx->max_sort_blocks, n_tasks);
     const dim3 cgrid(ctx->max_segs, n_tasks);
-    if (split) hipLaunchKernelGGL(k_tile_hist<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
-    else hipLaunchKernelGGL(k_tile_hist<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
-    hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, t);
-    hipLaunchKernelGGL(k_scan_segs, dim3(n_tasks), dim3(1024), 0, ctx->stream, t);
-    hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, t);
-    if (split) hipLaunchKernelGGL(k_tile_scatter<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
-    else hipLaunchKernelGGL(k_tile_scatter<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t);
-    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, t, n_tasks);
+    if (split) hipLaunchKernelGGL(k_tile_hist<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
+    else hipLaunchKernelGGL(k_tile_hist<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
+    hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, t, max_level);
+    hipLaunchKernelGGL(k_scan_segs, dim3(n_tasks), dim3(1024), 0, ctx->stream, t, max_level);
+    hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, t, max_level);
+    if (split) hipLaunchKernelGGL(k_tile_scatter<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
+    else hipLaunchKernelGGL(k_tile_scatter<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
+    hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, t, n_tasks, max_level);
     return hipGetLastError();
 }
 
