@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_PARTICLE = {"fp32": 48, "fp64": 80}   # read + write of the particle state
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_split_c3_traffic.md")
+TRAFFIC_WORKLOAD = "c3"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2307_11107_amd", "csrc", "particles.hip")
 COPY_BYTES = 1 << 30           # calibration copy: 1 GiB read + 1 GiB written
 
@@ -42,9 +43,11 @@ def copy_calibration():
     del x, y
 
 
-def measured_traffic(particles_per_launch):
+def measured_traffic(particles_per_launch, workload):
     """HBM bytes per push launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and this workload (else None)."""
+    if workload != TRAFFIC_WORKLOAD:
+        return None
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -139,6 +142,9 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=16)
     ap.add_argument("--ensemble-warmup", type=int, default=30)
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--c5-steps", type=int, default=20)
+    ap.add_argument("--c5-warmup", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the particle loop of this build runs on a single MI355X "
@@ -176,7 +182,7 @@ def main():
                                f"dt={w['dt']}/wpe; FP32 split push/gather/deposit, FP64 multigrid Poisson and tallies",
                    "particles_per_species": w["n_macro"], "grid": [w["n1"], w["n2"]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch, args.workload),
                      "kernel": "k_push_split (FP32 split push+gather+deposit, all species in one launch)", "avg_launch_ms": push_avg_ms,
                      "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"]},
         "breakdown_ms_per_step": {k: tm[k] / max(tm["steps"], 1) for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
@@ -211,6 +217,25 @@ def main():
                                       for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
             "mg_cycles_per_step": te["mg_cycles"] / max(te["steps"], 1),
             "schedule": re["schedule"], "balance_exact": re["balance_exact"]}
+    if not args.no_c5 and args.workload != "c5":
+        # the largest single grain (2048 x 1024 cells, 2e8 macro-particles per
+        # species): the push at four times the c3 state
+        w5 = WORKLOADS["c5"]
+        r5 = run_gpu([w5], "fp32", args.c5_steps, args.c5_warmup, stream)
+        t5 = r5["timing"]
+        p5 = t5["push_ms"] / max(t5["push_launches"], 1)
+        gb5 = BYTES_PER_PARTICLE["fp32"] * r5["particle_steps"] / max(t5["push_launches"], 1) / (p5 * 1e-3) / 1e9
+        out["c5"] = {
+            "workload": f"c5: alpha={w5['alpha']}, wce/wpe={w5['wce']}, grid {w5['n1']}x{w5['n2']}, "
+                        f"x1_out={w5['x1_out']}, lambdaD/R0={w5['kappa']}, {w5['n_macro']:.0e} macro-particles "
+                        f"per species, FP32 split, FP64 multigrid",
+            "value": r5["particle_steps"] / r5["elapsed"], "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * r5["elapsed"] / args.c5_steps,
+            "push_avg_launch_ms": p5, "push_GBps": gb5, "push_frac_of_hbm_peak": gb5 / HBM_PEAK_GBS,
+            "breakdown_ms_per_step": {k: t5[k] / max(t5["steps"], 1)
+                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+            "mg_cycles_per_step": t5["mg_cycles"] / max(t5["steps"], 1),
+            "balance_exact": r5["balance_exact"]}
     if not args.no_cpu_baseline:
         rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

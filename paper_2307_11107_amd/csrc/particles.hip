@@ -174,8 +174,8 @@ __device__ __forceinline__ gptr<T> slot4(T* base, int64_t p) {
     return (gptr<T>)((gptr<C>)gbl(reinterpret_cast<C*>(base)) + ((uint32_t)p << 2));
 }
 
-// The particle arrays stream through once per step: their loads and stores
-// are non-temporal, which keeps L2 for the field and the deposit.
+// The particle arrays stream through once per step: the push's loads and
+// stores of them are non-temporal, which keeps L2 for the field and the deposit.
 template <typename T>
 __device__ __forceinline__ T ld_stream(gptr<const T> a) { return __builtin_nontemporal_load(a); }
 template <typename T>
@@ -449,11 +449,11 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
         x1a[p] = FP64_DEAD;
         return st;
     }
-    x1a[p] = x1n;
-    x2a[p] = x2n;
-    vRa[p] = vRn;
-    vZa[p] = vZ;
-    vTa[p] = vTn;
+    st_stream(x1a + p, x1n);
+    st_stream(x2a + p, x2n);
+    st_stream(vRa + p, vRn);
+    st_stream(vZa + p, vZ);
+    st_stream(vTa + p, vTn);
     locate64(gp, x1n, x2n, i1n, i2n, f1n, f2n);
     return 0;
 }
@@ -793,8 +793,8 @@ __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, SplitKey& k
 }
 __device__ inline void load_key(const PBuf& b, int64_t p, int64_t n, PlainKey& k) {
     if (p < n) {
-        k.x1 = gbl(static_cast<const double*>(b.pos1))[p];
-        k.x2 = gbl(static_cast<const double*>(b.pos2))[p];
+        k.x1 = ld_stream(gbl(static_cast<const double*>(b.pos1)) + p);
+        k.x2 = ld_stream(gbl(static_cast<const double*>(b.pos2)) + p);
     } else {
         k.x1 = FP64_DEAD;
         k.x2 = 0.0;
@@ -826,9 +826,9 @@ __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, SplitSta
 }
 __device__ inline void load_fields(const PBuf& b, int64_t p, int64_t n, PlainState& q) {
     if (p >= n) return;
-    q.vR = gbl(static_cast<const double*>(b.vR))[p];
-    q.vZ = gbl(static_cast<const double*>(b.vZ))[p];
-    q.vT = gbl(static_cast<const double*>(b.vT))[p];
+    q.vR = ld_stream(gbl(static_cast<const double*>(b.vR)) + p);
+    q.vZ = ld_stream(gbl(static_cast<const double*>(b.vZ)) + p);
+    q.vT = ld_stream(gbl(static_cast<const double*>(b.vT)) + p);
 }
 
 __device__ inline void set_key(SplitState& q, const SplitKey& k) { q.c = k.c; }
