@@ -733,6 +733,40 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
     gbl(C.f)[idx] = 0.25 * acc;
 }
 
+// The same restriction from a level whose u is zero (every level below the
+// finest in a sawtooth cycle: the restriction into it cleared it), where the
+// residual is f itself: C.f = R F.f, C.u = 0.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_restrict_rhs(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
+               const MGState* __restrict__ ms) {
+    const MGDesc& F = fine[blockIdx.y];
+    const MGDesc& C = coarse[blockIdx.y];
+    if (C.n1 == 0 || !level_active(F, ms)) return;
+    const int n1c = C.n1, nxc = n1c + 1;
+    const int n2f = F.n2, nxf = F.n1 + 1;
+    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (idx >= C.nodes) return;
+    gbl(C.u)[idx] = 0.0;
+    const int J = idx / nxc, I = idx - J * nxc;
+    if (I == 0 || I == n1c) {
+        gbl(C.f)[idx] = 0.0;
+        return;
+    }
+    const gptr<const double> f = gbl(static_cast<const double*>(F.f));
+    double acc = 0.0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int j = 2 * J + dj;
+        if (j < 0 || j > n2f) continue;
+        const double wj = dj == 0 ? 1.0 : 0.5;
+        for (int di = -1; di <= 1; ++di) {
+            const int i = 2 * I + di;
+            const double wi = di == 0 ? 1.0 : 0.5;
+            acc += wj * wi * f[(size_t)j * nxf + i];
+        }
+    }
+    gbl(C.f)[idx] = 0.25 * acc;
+}
+
 // fine u += P uc (bilinear) on the fine unknowns
 __global__ void __launch_bounds__(MG_BLOCK)
 k_prolong_add(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
@@ -1046,8 +1080,8 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
         if (l == 0)
             hipLaunchKernelGGL(k_restrict_residual<FineStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
-        else
-            hipLaunchKernelGGL(k_restrict_residual<StoredStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
+        else  // level l's u was cleared by the restriction into it
+            hipLaunchKernelGGL(k_restrict_rhs, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G,
                                ctx->mgdesc + (size_t)(l + 1) * G, ctx->mgs);
         coarse_solve(ctx, l + 1);
