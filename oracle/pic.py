@@ -13,6 +13,10 @@ leaving through the outer boundary are removed; a Maxwellian flux is injected
 through the outer boundary.  Diagnostics: the electric force on the grain from
 the surface field, and the surface charge density from the normal field.
 
+With Config.boltzmann the electrons are not moved: their density is n0 exp(phi)
+(Section 2, last paragraph; the physical sign) and the field solve is the
+nonlinear one of poisson.solve_boltzmann, started from the current potential.
+
 Readings where the paper is silent (all shared with the device implementation,
 which is written separately):
   * units: R0, 1/omega_pe, v_te, Te/e, n0, me, e; kappa = lambda_De / R0;
@@ -81,6 +85,7 @@ class Config:
     seed: int = 0
     grain: int = 0
     species: list = dc_field(default_factory=list)
+    boltzmann: bool = False       # electrons as n0 exp(phi), not moved (species: the moved ones)
 
 
 def _max_sampled(f, npts=4097):
@@ -102,6 +107,7 @@ class Simulation:
         self.V = float(np.sum(self.vol))
         self.A_out = gridmod.outer_area(self.grid)
         self._solver = None
+        self._A = None
         self.key = key_for(cfg.seed, cfg.grain)
         a = cfg.alpha
         self.M_vol = _max_sampled(lambda x2: geo.r_of(cfg.x1_out, x2, a) ** 3 - geo.r_of(-1.0, x2, a) ** 3)
@@ -216,8 +222,15 @@ class Simulation:
 
     def solve_field(self, deps):
         rho = sum(self.cfg.species[s].q * n for s, n in enumerate(self.densities(deps)))
-        src = poisson.source_from_density(rho, self.cfg.kappa)
-        self.phi = self.solver.solve(src, self.cfg.phi_grain, self.cfg.phi_out)
+        if self.cfg.boltzmann:
+            # Boltzmann electrons: Newton from the current potential
+            if self._A is None:
+                self._A = poisson.assemble(self.grid)
+            self.phi, _ = poisson.solve_boltzmann(self.grid, self._A, rho, self.cfg.kappa, self.cfg.phi_grain,
+                                                  self.cfg.phi_out, phi0=self.phi)
+        else:
+            src = poisson.source_from_density(rho, self.cfg.kappa)
+            self.phi = self.solver.solve(src, self.cfg.phi_grain, self.cfg.phi_out)
         self.phi1, self.phi2 = field.nodal_gradient(self.phi, self.grid)
 
     def set_phi(self, phi):

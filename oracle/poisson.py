@@ -19,6 +19,12 @@ Readings (the paper does not spell these out):
     vanish (they carry 1 - x2^2), so the row keeps the d2/dx1^2 term and the
     d/dx2 term, the latter by the second-order one-sided difference
     (+-3 phi_j -+ 4 phi_{j-+1} +- phi_{j-+2}) / (2 h2).
+Boltzmann electrons (Section 2, last paragraph: the electrons are not moved,
+their density follows the Boltzmann relation instead): with n_e = n0 exp(phi)
+in these units (phi in Te/e, n0 = 1; the physical sign, electrons gather where
+phi is high), eq. (6) becomes Lap(phi) = -(1/kappa^2) (rho_p - exp(phi)), rho_p
+the charge density of the moved species, solved by Newton's method on the same
+discrete operator (solve_boltzmann).
 The linear system is factorised by sparse LU (SuperLU through scipy), the
 library routine standing in for the LAPACK LU the paper names, and each solve is
 followed by two steps of FP64 iterative refinement (as LAPACK's expert drivers
@@ -115,3 +121,36 @@ def source_from_density(charge_density, lambdaD_over_R0):
     """eq. (6) in normalised units: Lap(phi) = -(R0/lambda_D)^2 * rho,
     rho = sum_s q_s n_s (units of e n0)."""
     return -np.asarray(charge_density, dtype=np.float64) / (lambdaD_over_R0 ** 2)
+
+
+def solve_boltzmann(grid, A, rho_p, kappa, phi_grain, phi_out, phi0=None, tol=1e-14, max_newton=60):
+    """Newton's method for A phi = -(rho_p - exp(phi)) / kappa^2 on the unknown
+    nodes, phi = phi_grain / phi_out on the Dirichlet columns (A from assemble).
+    Each step solves J dphi = -F with J = A - diag(exp(phi)) / kappa^2 (unknown
+    rows) by sparse LU; stops when the update falls below tol * max|phi| and
+    returns (phi, newton steps)."""
+    nx = grid.n1 + 1
+    n = A.shape[0]
+    unknown = np.ones(n, dtype=bool)
+    unknown[0::nx] = False
+    unknown[grid.n1::nx] = False
+    bnd = np.zeros(n)
+    bnd[0::nx] = phi_grain
+    bnd[grid.n1::nx] = phi_out
+    src_p = source_from_density(np.asarray(rho_p, dtype=np.float64).ravel(), kappa)
+    if phi0 is None:
+        # linear start: the electron density held at n0
+        b = np.where(unknown, src_p + 1.0 / kappa ** 2, bnd)
+        phi = spla.spsolve(A.tocsc(), b)
+    else:
+        phi = np.array(phi0, dtype=np.float64).ravel().copy()
+        phi[~unknown] = bnd[~unknown]
+    for it in range(1, max_newton + 1):
+        e = np.where(unknown, np.exp(phi) / kappa ** 2, 0.0)
+        F = A @ phi - np.where(unknown, src_p + e, bnd)
+        J = (A - sp.diags(e)).tocsc()
+        d = spla.splu(J).solve(-F)
+        phi = phi + d
+        if np.max(np.abs(d)) <= tol * max(np.max(np.abs(phi)), 1.0):
+            return phi.reshape(grid.shape), it
+    raise RuntimeError("Newton did not converge")
