@@ -64,32 +64,33 @@ def measured_traffic(particles_per_launch, workload):
     return float(vals["hbm_bytes_per_particle_step"]) * particles_per_launch
 
 
-def grain_cfgs(grains):
+def grain_cfgs(grains, boltzmann=False):
     import paper_2307_11107_amd as apic
     cfgs = []
     for w in grains:
-        sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]),
-              apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])]
+        ions = apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])
+        sp = [ions] if boltzmann else [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]), ions]
         cfgs.append(apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"],
                                    kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"]))
     return cfgs
 
 
-def run_gpu(grains, precision, steps, warmup, stream, autotune=False):
+def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=False):
     """Loads every grain, runs `warmup` steps (the autotuner's steps among
     them), then times `steps` steps between device synchronisations."""
     import torch
     import paper_2307_11107_amd as apic
     prec = apic.APIC_FP32_SPLIT if precision == "fp32" else apic.APIC_FP64
-    ctx = apic.apic_init(grain_cfgs(grains), apic.opts(precision=prec, inject=True, stream=stream,
-                                                       autotune=autotune))
+    ns = 1 if boltzmann else 2
+    ctx = apic.apic_init(grain_cfgs(grains, boltzmann), apic.opts(precision=prec, inject=True, stream=stream,
+                                                                  autotune=autotune, boltzmann_electrons=boltzmann))
     try:
         for g in range(len(grains)):
-            for s in range(2):
+            for s in range(ns):
                 apic.apic_inject(ctx, g, s)
         apic.apic_step(ctx, warmup)
         torch.cuda.synchronize()
-        t0 = [apic.apic_tallies(ctx, g, 2, w["n2"]) for g, w in enumerate(grains)]
+        t0 = [apic.apic_tallies(ctx, g, ns, w["n2"]) for g, w in enumerate(grains)]
         apic.apic_set_profiling(ctx, True)
         torch.cuda.synchronize()
         start = time.perf_counter()
@@ -97,13 +98,13 @@ def run_gpu(grains, precision, steps, warmup, stream, autotune=False):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - start
         tm = apic.apic_timing(ctx)
-        t1 = [apic.apic_tallies(ctx, g, 2, w["n2"]) for g, w in enumerate(grains)]
+        t1 = [apic.apic_tallies(ctx, g, ns, w["n2"]) for g, w in enumerate(grains)]
         sched = apic.apic_schedule(ctx)
     finally:
         apic.apic_free(ctx)
     pushed = int(sum(sum(b["particle_steps"]) - sum(a["particle_steps"]) for a, b in zip(t0, t1)))
     balance = all(int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
-                  for t in t1 for s in range(2))
+                  for t in t1 for s in range(ns))
     return {"elapsed": elapsed, "particle_steps": pushed, "timing": tm, "balance_exact": balance,
             "schedule": sched}
 
@@ -143,6 +144,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=16)
     ap.add_argument("--ensemble-warmup", type=int, default=30)
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-boltzmann", action="store_true")
     ap.add_argument("--c5-steps", type=int, default=20)
     ap.add_argument("--c5-warmup", type=int, default=6)
     args = ap.parse_args()
@@ -236,6 +238,23 @@ def main():
                                       for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
             "mg_cycles_per_step": t5["mg_cycles"] / max(t5["steps"], 1),
             "balance_exact": r5["balance_exact"]}
+    if not args.no_boltzmann:
+        # the same grain and ions with Boltzmann electrons (not moved; the
+        # field solve is the Newton-multigrid one)
+        rb = run_gpu([w], "fp32", args.steps, args.warmup, stream, boltzmann=True)
+        tb = rb["timing"]
+        pb = tb["push_ms"] / max(tb["push_launches"], 1)
+        gbb = BYTES_PER_PARTICLE["fp32"] * rb["particle_steps"] / max(tb["push_launches"], 1) / (pb * 1e-3) / 1e9
+        out["boltzmann_electrons"] = {
+            "workload": f"{args.workload} grain and ions ({w['n_macro']:.0e} macro-particles), electrons "
+                        f"n0 exp(phi) (not moved), FP32 split, FP64 Newton-multigrid Poisson",
+            "value": rb["particle_steps"] / rb["elapsed"], "unit": "ion particle-steps/s",
+            "ms_per_step": 1e3 * rb["elapsed"] / args.steps, "push_avg_launch_ms": pb, "push_GBps": gbb,
+            "push_frac_of_hbm_peak": gbb / HBM_PEAK_GBS,
+            "breakdown_ms_per_step": {k: tb[k] / max(tb["steps"], 1)
+                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+            "mg_cycles_per_step": tb["mg_cycles"] / max(tb["steps"], 1),
+            "balance_exact": rb["balance_exact"]}
     if not args.no_cpu_baseline:
         rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

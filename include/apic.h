@@ -93,6 +93,13 @@ typedef struct {
     int32_t poisson_max_cycles; /* in-step multigrid cycle cap (0: 40)                     */
     int32_t autotune;           /* 1: the first steps choose the launch schedule (below)   */
     void* stream;               /* hipStream_t; NULL: default stream                       */
+    int32_t boltzmann_electrons; /* 1: electrons are not moved; their density is
+                                    n0 exp(e phi / Te) (Section 2, last paragraph), so
+                                    eq. (6) is nonlinear in phi and solved by Newton's
+                                    method with the FP64 multigrid; the grain configs
+                                    then list the moved species only.  The grid must
+                                    coarsen (halving both cell counts) to <= 88 nodes,
+                                    else APIC_ERANGE                                      */
 } apic_opts;
 
 /* Grain tallies (Sections 1-2: currents, drag, torque and heat flux follow from

@@ -123,11 +123,12 @@ def source_from_density(charge_density, lambdaD_over_R0):
     return -np.asarray(charge_density, dtype=np.float64) / (lambdaD_over_R0 ** 2)
 
 
-def solve_boltzmann(grid, A, rho_p, kappa, phi_grain, phi_out, phi0=None, tol=1e-14, max_newton=60):
+def solve_boltzmann(grid, A, rho_p, kappa, phi_grain, phi_out, phi0=None, tol=1e-12, max_newton=60):
     """Newton's method for A phi = -(rho_p - exp(phi)) / kappa^2 on the unknown
     nodes, phi = phi_grain / phi_out on the Dirichlet columns (A from assemble).
     Each step solves J dphi = -F with J = A - diag(exp(phi)) / kappa^2 (unknown
-    rows) by sparse LU; stops when the update falls below tol * max|phi| and
+    rows) by sparse LU with two steps of iterative refinement (as in
+    PoissonSolver); stops when the update falls below tol * max|phi| and
     returns (phi, newton steps)."""
     nx = grid.n1 + 1
     n = A.shape[0]
@@ -149,7 +150,10 @@ def solve_boltzmann(grid, A, rho_p, kappa, phi_grain, phi_out, phi0=None, tol=1e
         e = np.where(unknown, np.exp(phi) / kappa ** 2, 0.0)
         F = A @ phi - np.where(unknown, src_p + e, bnd)
         J = (A - sp.diags(e)).tocsc()
-        d = spla.splu(J).solve(-F)
+        lu = spla.splu(J)
+        d = lu.solve(-F)
+        for _ in range(2):
+            d = d + lu.solve(-F - J @ d)
         phi = phi + d
         if np.max(np.abs(d)) <= tol * max(np.max(np.abs(phi)), 1.0):
             return phi.reshape(grid.shape), it

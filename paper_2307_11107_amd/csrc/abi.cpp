@@ -159,7 +159,7 @@ int read_batch(apic_ctx* ctx, MGBatch& b) {
 // also stop at stagnation.  In-step solves replay the captured V-cycle as many
 // times as the previous solve needed before reading the convergence state once
 // (cycles after convergence do nothing on the device).
-int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
+int solve_linear(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
     MGBatch b;
     int launched = 0;
     if (in_step) {
@@ -208,6 +208,87 @@ int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bo
     }
     if (cycles) *cycles = b.max_cycles;
     return APIC_OK;
+}
+
+// Largest relative residual |D^-1 r| / |D^-1 b| of the grains solved, from the
+// last convergence check.
+int max_rel_residual(apic_ctx* ctx, int only, double& r) {
+    const int G = (int)ctx->grains.size();
+    std::vector<MGState> m(G);
+    HIPCHK(ctx, hipMemcpy(m.data(), ctx->mgs, sizeof(MGState) * G, hipMemcpyDeviceToHost));
+    r = 0.0;
+    for (int g = 0; g < G; ++g)
+        if (only < 0 || g == only) r = std::max(r, std::sqrt(m[g].last_r2 / (m[g].b2 + ctx->gdesc_h[g].bnd2 + 1e-300)));
+    return APIC_OK;
+}
+
+// Boltzmann electrons: Newton's method on eq. (6) with n_e = exp(phi).  Each
+// step linearises about the current phi (on every level, with the coarsest
+// inverses formed again), runs V-cycles to the tolerance and limits the change
+// of phi (damped Newton); the residual of a linearisation at its own starting
+// point is the nonlinear residual, so the iteration ends when a step starts
+// converged (or, solving to round-off, when that residual reaches round-off
+// and stops falling).  In-step solves start from the extrapolated potential of
+// the previous steps.
+constexpr int MAX_NEWTON = 40;
+
+int solve_newton(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
+    if (in_step) {
+        HIPCHK(ctx, launch_rho_rhs(ctx));
+        HIPCHK(ctx, mg_extrapolate(ctx));
+    }
+    HIPCHK(ctx, launch_set_boundary(ctx));
+    MGBatch b;
+    int total = 0;
+    double prev = HUGE_VAL;
+    bool converged = false;
+    for (int it = 0; it < MAX_NEWTON && !converged; ++it) {
+        HIPCHK(ctx, newton_prepare(ctx, only));
+        HIPCHK(ctx, mg_begin(ctx, tol, only, in_step));
+        TRY(read_batch(ctx, b));
+        if (b.nan) break;
+        if (b.pending == 0) {
+            converged = true;
+            break;
+        }
+        double r0 = 0.0;
+        TRY(max_rel_residual(ctx, only, r0));
+        if (to_floor && (r0 <= 1e-13 || (it >= 3 && r0 < 1e-11 && r0 > 0.5 * prev))) {
+            converged = true;
+            break;
+        }
+        prev = r0;
+        int launched = 0;
+        double last = HUGE_VAL;
+        while (b.pending > 0 && launched < max_cycles) {
+            if (in_step) TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+            else HIPCHK(ctx, mg_vcycle_launches(ctx, tol));
+            ++launched;
+            TRY(read_batch(ctx, b));
+            if (to_floor) {
+                double r = 0.0;
+                TRY(max_rel_residual(ctx, only, r));
+                if (launched >= 4 && r > 0.6 * last) break;
+                last = r;
+            }
+        }
+        HIPCHK(ctx, newton_limit(ctx, only));
+        total += launched;
+        if (b.nan) break;
+    }
+    if (b.nan) {
+        HIPCHK(ctx, launch_fill(ctx, &ctx->mgb->nan, sizeof(int)));
+        return fail(ctx, APIC_EDEVICE, "Poisson solve produced NaN");
+    }
+    if (!converged) return fail(ctx, APIC_EDEVICE, "Boltzmann-electron Newton iteration did not converge");
+    if (cycles) *cycles = total;
+    return APIC_OK;
+}
+
+int solve(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
+    if (ctx->opts.boltzmann_electrons)
+        return solve_newton(ctx, tol, max_cycles, to_floor, only, in_step, cycles);
+    return solve_linear(ctx, tol, max_cycles, to_floor, only, in_step, cycles);
 }
 
 // Deposit the current particles of every grain and solve for phi.
@@ -267,6 +348,8 @@ void free_grain(Grain& g) {
         F(L.uT);
         F(L.fT);
         F(L.uprev);
+        F(L.shift);
+        F(L.uold);
     }
     g.mg.clear();
     g.ctr = nullptr;
@@ -335,6 +418,7 @@ struct HostSetup {
     std::vector<double> inv;
     int max_dense = 600;        // largest level solved by the dense inverse
     int threads = 1;            // host threads for the inverse
+    bool boltzmann = false;     // Newton term on every level: the coarsest inverse is formed on the device
     int rc = APIC_OK;
     std::string err;
 };
@@ -345,6 +429,8 @@ struct HostSetup {
 // large as the ensemble's inverses allow: about 192 MB of them in total, at
 // most 4400 nodes (65 x 65) and at least 600 per grain.
 constexpr int DENSE_MAX_NODES = 4400;
+// With Boltzmann electrons the coarsest operator changes with every Newton step
+// and is inverted on the device, in one workgroup's LDS (BOLTZ_INV_MAX nodes).
 int dense_limit(int n_grains) {
     const double per = 192.0 * (1 << 20) / (8.0 * n_grains);
     return std::max(600, std::min(DENSE_MAX_NODES, (int)std::sqrt(per)));
@@ -427,7 +513,8 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     // enough.
     hs.levels.resize(1);
     fine_stencil(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
-    while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > (hs.levels.size() == 1 ? 600 : hs.max_dense) &&
+    const int fine_dense = std::min(600, hs.max_dense);
+    while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > (hs.levels.size() == 1 ? fine_dense : hs.max_dense) &&
            hs.levels.back().n1 % 2 == 0 &&
            hs.levels.back().n2 % 2 == 0 && std::min(hs.levels.back().n1, hs.levels.back().n2) / 2 >= 4) {
         Stencil cs;
@@ -436,17 +523,20 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     }
     const Stencil& last = hs.levels.back();
     const int m = (last.n1 + 1) * (last.n2 + 1);
-    if (m > DENSE_MAX_NODES) {
+    if (m > (hs.boltzmann ? BOLTZ_INV_MAX : DENSE_MAX_NODES)) {
         hs.rc = APIC_ERANGE;
-        hs.err = "grid does not coarsen far enough for multigrid";
+        hs.err = hs.boltzmann ? "grid does not coarsen to 88 nodes for the Boltzmann-electron solve"
+                              : "grid does not coarsen far enough for multigrid";
         return;
     }
-    std::vector<double> A;
-    dense_matrix(last, A);
-    if (!invert(A, m, hs.inv, hs.threads)) {
-        hs.rc = APIC_EDEVICE;
-        hs.err = "coarsest multigrid operator is singular";
-        return;
+    if (!hs.boltzmann) {
+        std::vector<double> A;
+        dense_matrix(last, A);
+        if (!invert(A, m, hs.inv, hs.threads)) {
+            hs.rc = APIC_EDEVICE;
+            hs.err = "coarsest multigrid operator is singular";
+            return;
+        }
     }
     g.coarse_nodes = m;
     g.bnd_norm2 = boundary_coupling_norm2(hs.levels[0], c.phi_grain, c.phi_out);
@@ -506,6 +596,11 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
         TRY(alloc_t(ctx, &L.f, (size_t)L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.u, sizeof(double) * L.nodes));
         HIPCHK(ctx, launch_fill(ctx, L.f, sizeof(double) * L.nodes));
+        if (hs.boltzmann) {
+            TRY(alloc_t(ctx, &L.shift, (size_t)L.nodes));
+            HIPCHK(ctx, launch_fill(ctx, L.shift, sizeof(double) * L.nodes));
+            if (l == 0) TRY(alloc_t(ctx, &L.uold, (size_t)L.nodes));
+        }
         if (l == 0) {
             // the finest operator is evaluated at the nodes; its x2 sweeps may
             // use transposed copies of u and f
@@ -520,9 +615,10 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             std::copy(hs.levels[l].c[k].begin(), hs.levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
         HIPCHK(ctx, hipMemcpy(L.st, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice));
     }
-    HIPCHK(ctx, hipMemcpy2DAsync(g.coarse_inv, sizeof(double) * inv_pitch, hs.inv.data(),
-                                 sizeof(double) * g.coarse_nodes, sizeof(double) * g.coarse_nodes, g.coarse_nodes,
-                                 hipMemcpyHostToDevice, ctx->stream));
+    if (!hs.inv.empty())
+        HIPCHK(ctx, hipMemcpy2DAsync(g.coarse_inv, sizeof(double) * inv_pitch, hs.inv.data(),
+                                     sizeof(double) * g.coarse_nodes, sizeof(double) * g.coarse_nodes,
+                                     g.coarse_nodes, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return APIC_OK;
 }
@@ -677,6 +773,8 @@ int build_tables(apic_ctx* ctx) {
             d.fT = L.fT;
             d.uprev = L.uprev;
             d.inv = d.coarsest ? g.coarse_inv : nullptr;
+            d.shift = L.shift;
+            d.uold = L.uold;
             ctx->lvl_max_nodes[l] = std::max(ctx->lvl_max_nodes[l], L.nodes);
             if (!d.coarsest) {
                 ctx->lvl_max_n1[l] = std::max(ctx->lvl_max_n1[l], L.n1);
@@ -999,7 +1097,8 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         const int hw = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
         const int nt = std::min(n_grains, hw);
         for (auto& h : hs) {
-            h.max_dense = dense_limit(n_grains);
+            h.boltzmann = ctx->opts.boltzmann_electrons != 0;
+            h.max_dense = h.boltzmann ? BOLTZ_INV_MAX : dense_limit(n_grains);
             h.threads = std::max(1, hw / nt);
         }
         std::vector<std::thread> pool;

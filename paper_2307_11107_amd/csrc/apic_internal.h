@@ -129,6 +129,9 @@ struct MGDesc {
     double* fT;
     double* uprev;              // finest level: the potential of the previous step
     const double* inv;          // dense inverse (coarsest only)
+    const double* shift;        // Boltzmann electrons: the Newton term subtracted from the
+                                // operator's diagonal (nullptr: none)
+    double* uold;               // Boltzmann electrons, finest level: phi before the Newton step
 };
 
 // Convergence state of the in-step multigrid solves, per grain.
@@ -158,6 +161,8 @@ struct MGLevel {
     double* uT = nullptr;       // finest level: u, f transposed for the x2 sweeps
     double* fT = nullptr;
     double* uprev = nullptr;    // finest level: previous step's potential
+    double* shift = nullptr;    // Boltzmann electrons: diagonal Newton term of this level
+    double* uold = nullptr;     // Boltzmann electrons, finest level: phi before the Newton step
 };
 
 struct Grain {
@@ -211,6 +216,9 @@ struct TuneState {
 
 struct TimerPair { hipEvent_t a, b; int kind; };
 
+// Boltzmann electrons: largest coarsest level, inverted in one workgroup's LDS
+// (88^2 doubles and the pivot scratch stay within 64 KiB)
+constexpr int BOLTZ_INV_MAX = 88;
 constexpr int SORT_LEVELS = 5;   // a slow species is sorted up to 16x less often
 enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_SORT, G_COUNT = G_SORT + SORT_LEVELS };
 
@@ -293,6 +301,8 @@ hipError_t launch_set_boundary(apic_ctx* ctx);
 
 // multigrid.hip
 hipError_t mg_extrapolate(apic_ctx* ctx);
+hipError_t newton_prepare(apic_ctx* ctx, int only);
+hipError_t newton_limit(apic_ctx* ctx, int only);
 hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step);
 hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol);
 

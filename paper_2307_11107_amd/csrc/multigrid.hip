@@ -165,14 +165,18 @@ struct Coef {
 };
 
 // Coarse levels: the Galerkin stencil arrays.
+// With Boltzmann electrons every level's diagonal carries the Newton term
+// (`shift`, subtracted from the centre coefficient).
 struct StoredStencil {
     gptr<const double> st;
+    const double* sh;
     int nodes, n2;
-    __device__ explicit StoredStencil(const MGDesc& D) : st(gbl(D.st)), nodes(D.nodes), n2(D.n2) {}
+    __device__ explicit StoredStencil(const MGDesc& D) : st(gbl(D.st)), sh(D.shift), nodes(D.nodes), n2(D.n2) {}
     __device__ Coef at(int, int, size_t o) const {
         const size_t n = (size_t)nodes;
         Coef c;
         c.C = st[ST_C * n + o];
+        if (sh) c.C -= gbl(sh)[o];
         c.W = st[ST_W * n + o];
         c.E = st[ST_E * n + o];
         c.S = st[ST_S * n + o];
@@ -185,7 +189,9 @@ struct StoredStencil {
         c.ss = 0.0;
         return c;
     }
-    __device__ double diag(int, int, size_t o) const { return st[ST_C * (size_t)nodes + o]; }
+    __device__ double diag(int, int, size_t o) const {
+        return st[ST_C * (size_t)nodes + o] - (sh ? gbl(sh)[o] : 0.0);
+    }
 };
 
 // Finest level: the central differences of eq. (7) evaluated at the node
@@ -195,11 +201,12 @@ struct StoredStencil {
 // level.
 struct FineStencil {
     double a, h1, h2, ih1sq, ih2sq, i2h2, i4h1h2;
+    const double* sh;
     int n2;
     __device__ explicit FineStencil(const MGDesc& D)
         : a(D.alpha), h1(D.h1), h2(D.h2), ih1sq(1.0 / (D.h1 * D.h1)), ih2sq(1.0 / (D.h2 * D.h2)),
-          i2h2(1.0 / (2.0 * D.h2)), i4h1h2(1.0 / (4.0 * D.h1 * D.h2)), n2(D.n2) {}
-    __device__ Coef at(int j, int i, size_t) const {
+          i2h2(1.0 / (2.0 * D.h2)), i4h1h2(1.0 / (4.0 * D.h1 * D.h2)), sh(D.shift), n2(D.n2) {}
+    __device__ Coef at(int j, int i, size_t o) const {
         const double x1 = -1.0 + i * h1, x2 = -1.0 + j * h2;
         const double r = -(1.0 + sqrt(1.0 - 4.0 * a * x1 * x2)) / (2.0 * x1);
         const bool edge = (j == 0 || j == n2);
@@ -235,6 +242,7 @@ struct FineStencil {
             c.NW = -a12;
             c.SE = -a12;
         }
+        if (sh) c.C -= gbl(sh)[o];
         return c;
     }
     __device__ double diag(int j, int i, size_t o) const { return at(j, i, o).C; }
@@ -522,7 +530,7 @@ k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int c
     const size_t base = (size_t)i * L;
     for (int j = threadIdx.x; j < L; j += NT) {
         const size_t o = base + j;
-        const Coef k = st.at(j, i, 0);
+        const Coef k = st.at(j, i, (size_t)j * (n1 + 1) + i);
         double rhs = ft[o] - k.W * ut[o - L] - k.E * ut[o + L];
         if (j > 0) rhs -= k.SW * ut[o - L - 1] + k.SE * ut[o + L - 1];
         if (j < n2) rhs -= k.NW * ut[o - L + 1] + k.NE * ut[o + L + 1];
@@ -1059,6 +1067,228 @@ hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step) {
                        ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
     residual_check(ctx, tol, 0, true);
     if (ctx->x2_transposed) transpose<2>(ctx);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Boltzmann electrons
+// With n_e = exp(phi) (units n0, Te/e), eq. (6) reads A phi = s rho_p - s exp(phi),
+// s = -1/kappa^2 (rhs_scale).  A Newton step linearises exp about the current
+// phi: (A - E) phi' = s rho_p + E (1 - phi) with E = -s exp(phi) on the unknown
+// nodes.  The multigrid solves it with E subtracted from every level's diagonal:
+// on the finest level E itself, on each coarser one the full-weighting average
+// of the level above (the row sums of the Galerkin product R E P, as P carries
+// a constant to a constant), and the coarsest level's dense inverse is formed
+// again on the device.
+__global__ void __launch_bounds__(MG_BLOCK)
+k_newton_prepare(const GrainDesc* __restrict__ gd, const MGDesc* __restrict__ lv, int only) {
+    const GrainDesc& G = gd[blockIdx.y];
+    const MGDesc& D = lv[blockIdx.y];
+    if (only >= 0 && (int)blockIdx.y != only) return;
+    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (idx >= D.nodes) return;
+    const int i = idx % D.nx;
+    double* sh = const_cast<double*>(D.shift);
+    if (i == 0 || i == D.n1) {
+        gbl(sh)[idx] = 0.0;
+        return;
+    }
+    const double u = gbl(static_cast<const double*>(D.u))[idx];
+    const double e = -G.rhs_scale * exp(u);
+    gbl(D.uold)[idx] = u;
+    gbl(sh)[idx] = e;
+    gbl(D.f)[idx] = G.rhs_scale * gbl(static_cast<const double*>(G.rho))[idx] + e * (1.0 - u);
+}
+
+__global__ void __launch_bounds__(MG_BLOCK)
+k_restrict_shift(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse, int only) {
+    const MGDesc& F = fine[blockIdx.y];
+    const MGDesc& C = coarse[blockIdx.y];
+    if (C.n1 == 0 || (only >= 0 && (int)blockIdx.y != only)) return;
+    const int n1c = C.n1, nxc = n1c + 1;
+    const int n2f = F.n2, nxf = F.n1 + 1;
+    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (idx >= C.nodes) return;
+    const int J = idx / nxc, I = idx - J * nxc;
+    double* out = const_cast<double*>(C.shift);
+    if (I == 0 || I == n1c) {
+        gbl(out)[idx] = 0.0;
+        return;
+    }
+    const gptr<const double> e = gbl(F.shift);
+    double acc = 0.0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int j = 2 * J + dj;
+        if (j < 0 || j > n2f) continue;
+        const double wj = dj == 0 ? 1.0 : 0.5;
+        for (int di = -1; di <= 1; ++di) {
+            const double wi = di == 0 ? 1.0 : 0.5;
+            acc += wj * wi * e[(size_t)j * nxf + 2 * I + di];
+        }
+    }
+    gbl(out)[idx] = 0.25 * acc;
+}
+
+// Dense inverse of a grain's coarsest operator (with its Newton term) in one
+// workgroup: the m x m matrix (identity rows on the Dirichlet columns) is
+// assembled in LDS and inverted in place by Gauss-Jordan elimination with
+// partial pivoting (the row interchanges are undone on the columns of the
+// inverse at the end), then written with rows padded to an even length.
+constexpr int INV_BLOCK = 256;
+
+template <class ST>
+__global__ void __launch_bounds__(INV_BLOCK)
+k_coarse_invert(const MGDesc* __restrict__ lv, int only) {
+    extern __shared__ double M[];
+    __shared__ double colk[BOLTZ_INV_MAX];
+    __shared__ int piv[BOLTZ_INV_MAX];
+    __shared__ int prow;
+    const MGDesc& D = lv[blockIdx.y];
+    if (D.n1 == 0 || !D.coarsest || (only >= 0 && (int)blockIdx.y != only)) return;
+    const int m = D.m, nx = D.n1 + 1, n2 = D.n2;
+    if (m > BOLTZ_INV_MAX) return;   // the host never builds such a level
+    for (int t = threadIdx.x; t < m * m; t += INV_BLOCK) M[t] = 0.0;
+    __syncthreads();
+    const ST st(D);
+    for (int o = threadIdx.x; o < m; o += INV_BLOCK) {
+        const int j = o / nx, i = o - j * nx;
+        double* row = M + (size_t)o * m;
+        if (i == 0 || i == D.n1) {
+            row[o] = 1.0;
+            continue;
+        }
+        const Coef k = st.at(j, i, o);
+        row[o] = k.C;
+        row[o - 1] = k.W;
+        row[o + 1] = k.E;
+        if (j > 0) {
+            row[o - nx] = k.S;
+            row[o - nx - 1] = k.SW;
+            row[o - nx + 1] = k.SE;
+        }
+        if (j < n2) {
+            row[o + nx] = k.N;
+            row[o + nx - 1] = k.NW;
+            row[o + nx + 1] = k.NE;
+        }
+        if (j == 0) row[o + 2 * nx] += k.nn;
+        if (j == n2) row[o - 2 * nx] += k.ss;
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        if (threadIdx.x < 64) {
+            // pivot: largest |M[r][k]|, r >= k (first of equal ones)
+            double best = -1.0;
+            int br = k;
+            for (int r = k + (int)threadIdx.x; r < m; r += 64) {
+                const double v = fabs(M[(size_t)r * m + k]);
+                if (v > best) {
+                    best = v;
+                    br = r;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(best, off);
+                const int orow = __shfl_xor(br, off);
+                if (ov > best || (ov == best && orow < br)) {
+                    best = ov;
+                    br = orow;
+                }
+            }
+            if (threadIdx.x == 0) {
+                prow = br;
+                piv[k] = br;
+            }
+        }
+        __syncthreads();
+        const int p = prow;
+        if (p != k)
+            for (int c = threadIdx.x; c < m; c += INV_BLOCK) {
+                const double t = M[(size_t)k * m + c];
+                M[(size_t)k * m + c] = M[(size_t)p * m + c];
+                M[(size_t)p * m + c] = t;
+            }
+        __syncthreads();
+        const double pinv = 1.0 / M[(size_t)k * m + k];
+        for (int r = threadIdx.x; r < m; r += INV_BLOCK) colk[r] = M[(size_t)r * m + k];
+        __syncthreads();
+        for (int c = threadIdx.x; c < m; c += INV_BLOCK)
+            M[(size_t)k * m + c] = (c == k ? 1.0 : M[(size_t)k * m + c]) * pinv;
+        __syncthreads();
+        for (int t = threadIdx.x; t < m * m; t += INV_BLOCK) {
+            const int r = t / m, c = t - r * m;
+            if (r == k) continue;
+            M[t] = (c == k ? 0.0 : M[t]) - M[(size_t)k * m + c] * colk[r];
+        }
+        __syncthreads();
+    }
+    // undo the row interchanges on the columns, last first
+    for (int k = m - 1; k >= 0; --k) {
+        const int p = piv[k];
+        if (p != k)
+            for (int r = threadIdx.x; r < m; r += INV_BLOCK) {
+                const double t = M[(size_t)r * m + k];
+                M[(size_t)r * m + k] = M[(size_t)r * m + p];
+                M[(size_t)r * m + p] = t;
+            }
+        __syncthreads();
+    }
+    const int mp = (m + 1) & ~1;
+    double* inv = const_cast<double*>(D.inv);
+    for (int t = threadIdx.x; t < m * mp; t += INV_BLOCK) {
+        const int r = t / mp, c = t - r * mp;
+        gbl(inv)[t] = c < m ? M[(size_t)r * m + c] : 0.0;
+    }
+}
+
+// Damped Newton: a step changes phi by at most NEWTON_MAX_STEP (Te/e) at any
+// node.  Far from the solution (a new density, a first solve) the linearised
+// exp(phi) badly underestimates the growth of the electron density where phi
+// rises, and a full step overshoots; near it the limit never acts.
+constexpr double NEWTON_MAX_STEP = 1.0;
+
+__global__ void __launch_bounds__(MG_BLOCK)
+k_newton_limit(const MGDesc* __restrict__ lv, int only) {
+    const MGDesc& D = lv[blockIdx.y];
+    if (only >= 0 && (int)blockIdx.y != only) return;
+    const int idx = blockIdx.x * MG_BLOCK + threadIdx.x;
+    if (idx >= D.nodes) return;
+    const int i = idx % D.nx;
+    if (i == 0 || i == D.n1) return;
+    const double u0 = gbl(D.uold)[idx];
+    const double d = gbl(D.u)[idx] - u0;
+    if (d > NEWTON_MAX_STEP) gbl(D.u)[idx] = u0 + NEWTON_MAX_STEP;
+    else if (d < -NEWTON_MAX_STEP) gbl(D.u)[idx] = u0 - NEWTON_MAX_STEP;
+}
+
+hipError_t newton_limit(apic_ctx* ctx, int only) {
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL(k_newton_limit, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, only);
+    return hipGetLastError();
+}
+
+// The Newton linearisation about the current phi on every level, and the
+// coarsest inverses.
+hipError_t newton_prepare(apic_ctx* ctx, int only) {
+    const int G = (int)ctx->grains.size();
+    const int nl = ctx->n_levels;
+    hipLaunchKernelGGL(k_newton_prepare, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->gdesc,
+                       ctx->mgdesc, only);
+    for (int l = 0; l + 1 < nl; ++l) {
+        const int cn = ctx->lvl_max_nodes[l + 1];
+        hipLaunchKernelGGL(k_restrict_shift, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
+                           ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G, only);
+    }
+    for (int l = 0; l < nl; ++l) {
+        const int m = ctx->lvl_max_m[l];
+        if (m <= 0) continue;
+        const size_t lds = sizeof(double) * (size_t)m * m;
+        if (l == 0)
+            hipLaunchKernelGGL(k_coarse_invert<FineStencil>, dim3(1, G), dim3(INV_BLOCK), lds, ctx->stream,
+                               ctx->mgdesc, only);
+        else
+            hipLaunchKernelGGL(k_coarse_invert<StoredStencil>, dim3(1, G), dim3(INV_BLOCK), lds, ctx->stream,
+                               ctx->mgdesc + (size_t)l * G, only);
+    }
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ def species_pair(w, electrons=True, ions=True, weight=0.0, n_macro=None):
 
 
 def make_pair(w, precision, inject=True, frozen=False, electrons=True, ions=True, weight=0.0,
-              n_macro=None, n_bins=0, sort_every=0, poisson_tol=0.0, capacity=0):
+              n_macro=None, n_bins=0, sort_every=0, poisson_tol=0.0, capacity=0, boltzmann=False):
     dev_sp, ora_sp = species_pair(w, electrons, ions, weight, n_macro)
     if capacity:
         for s in dev_sp:
@@ -29,9 +29,11 @@ def make_pair(w, precision, inject=True, frozen=False, electrons=True, ions=True
                          kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], n_bins=n_bins,
                          seed=w["seed"])
     ctx = apic.apic_init([cfg], apic.opts(precision=precision, inject=inject, frozen_field=frozen,
-                                          sort_every=sort_every, poisson_tol=poisson_tol))
+                                          sort_every=sort_every, poisson_tol=poisson_tol,
+                                          boltzmann_electrons=boltzmann))
     ocfg = Config(alpha=w["alpha"], n1=w["n1"], n2=w["n2"], x1_out=w["x1_out"], wce=w["wce"],
-                  kappa=w["kappa"], dt=w["dt"], n_bins=n_bins, seed=w["seed"], species=ora_sp)
+                  kappa=w["kappa"], dt=w["dt"], n_bins=n_bins, seed=w["seed"], species=ora_sp,
+                  boltzmann=boltzmann)
     sim = Simulation(ocfg)
     sim.inject_enabled = inject
     sim.frozen = frozen

@@ -1,0 +1,90 @@
+"""Boltzmann-electron mode on the GPU (electrons not moved, n_e = n0 exp(phi);
+Section 2, last paragraph) against the oracle's Newton solve and its ions-only
+time loop, through the C ABI."""
+import numpy as np
+import pytest
+
+import paper_2307_11107_amd as apic
+from gpu_util import make_pair, particle_error
+from oracle.grid import Grid
+from oracle.poisson import assemble, solve_boltzmann
+from synthetic_inputs import WORKLOADS, smooth_density
+
+pytestmark = pytest.mark.gpu
+
+# (n1, n2, alpha, x1_out, lambda_D / R0)
+CASES = [(64, 64, 0.2, -0.1, 1.0), (128, 96, -0.15, -0.2, 0.5), (256, 128, 0.1, -0.1, 2.0),
+         (512, 512, 0.2, -0.1, 1.0)]
+
+
+def _ctx(n1, n2, alpha, xo, kappa, precision=apic.APIC_FP64):
+    sp = [apic.species(1.0, 100.0, 1.0, 1.0, 0.0, 0.0, 0)]
+    cfg = apic.grain_cfg(alpha, n1, n2, sp, x1_out=xo, kappa=kappa, phi_grain=-2.5, phi_out=0.0)
+    return apic.apic_init([cfg], apic.opts(precision=precision, inject=False, boltzmann_electrons=True))
+
+
+@pytest.mark.parametrize("n1,n2,alpha,xo,kappa", CASES)
+def test_nonlinear_solve_matches_oracle(n1, n2, alpha, xo, kappa):
+    """A smooth ion density of 0.7..1.3 n0: the device's Newton-multigrid
+    solve to round-off against the oracle's Newton-LU solve (1e-10 of max|phi|)."""
+    print(f"boltzmann solve n1={n1} n2={n2} alpha={alpha} kappa={kappa}", flush=True)
+    rho = 1.0 + 0.1 * smooth_density(n1, n2, seed=n1 + 7 * n2)
+    ctx = _ctx(n1, n2, alpha, xo, kappa)
+    try:
+        phi = apic.apic_solve_poisson(ctx, 0, rho, shape=(n2 + 1, n1 + 1)).reshape(n2 + 1, n1 + 1)
+    finally:
+        apic.apic_free(ctx)
+    g = Grid(n1, n2, xo, alpha)
+    ref, _ = solve_boltzmann(g, assemble(g), rho, kappa, -2.5, 0.0)
+    err = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+    print(f"  max rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_grid_that_does_not_coarsen_far_enough_is_rejected():
+    """The coarsest level is inverted in one workgroup (at most 88 nodes):
+    100 x 100 cells stop coarsening at 25 x 25."""
+    with pytest.raises(RuntimeError, match="88 nodes"):
+        _ctx(100, 100, 0.1, -0.1, 1.0)
+
+
+@pytest.mark.parametrize("precision", [apic.APIC_FP64, apic.APIC_FP32_SPLIT])
+def test_ions_only_run_matches_oracle(precision):
+    """The small spherical workload (64 x 64 cells) with the ions moved
+    (1e5 macro-particles, injection) and Boltzmann electrons, 30 self-consistent
+    steps: exact bookkeeping, the same absorbed and escaped ions, the potential
+    and every ion (by id) as in the oracle's run."""
+    w = dict(WORKLOADS["c1"])
+    steps = 30
+    print(f"boltzmann c1 run precision={precision}", flush=True)
+    ctx, sim = make_pair(w, precision, inject=True, electrons=False, boltzmann=True)
+    try:
+        apic.apic_inject(ctx, 0, 0)
+        sim.load(0)
+        sim.initialize_field()
+        apic.apic_step(ctx, steps)
+        sim.run(steps)
+        t = apic.apic_tallies(ctx, 0, 1, w["n2"])
+        phi, _ = apic.apic_fields(ctx, 0, (w["n2"] + 1, w["n1"] + 1))
+        res = int(t["resident"][0])
+        dev = apic.apic_particles(ctx, 0, 0, res + 16)
+    finally:
+        apic.apic_free(ctx)
+    assert int(t["injected"][0]) == int(t["absorbed"][0] + t["escaped"][0] + t["resident"][0])
+    assert int(t["injected"][0]) == int(sim.injected[0]) + w["n_macro"]
+    na, nb = int(t["absorbed"][0]), int(sim.absorbed[0])
+    ea, eb = int(t["escaped"][0]), int(sim.escaped[0])
+    rel = np.max(np.abs(phi - sim.phi)) / np.max(np.abs(sim.phi))
+    ora = sim.particles(0)
+    err, common = particle_error(dev, ora, sim.grid, np.sqrt(w["Ti"] / w["mi"]))
+    mismatch = len(dev["id"]) + len(ora["id"]) - 2 * common
+    print(f"absorbed gpu {na} oracle {nb}; escaped gpu {ea} oracle {eb}; phi rel diff {rel:.2e}; "
+          f"particles {common} median {np.median(err):.2e} max {err.max():.2e} mismatch {mismatch}")
+    if precision == apic.APIC_FP64:
+        assert (na, ea) == (nb, eb) and mismatch == 0
+        assert rel < 1e-8
+        assert np.quantile(err, 0.999) < 1e-8
+    else:
+        assert abs(na - nb) <= 2 and abs(ea - eb) <= 2 and mismatch <= 4
+        assert rel < 1e-4
+        assert np.median(err) < 1e-6 and np.quantile(err, 0.999) < 1e-4
