@@ -243,7 +243,33 @@ int solve_newton(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int o
     double prev = HUGE_VAL;
     bool converged = false;
     for (int it = 0; it < MAX_NEWTON && !converged; ++it) {
-        HIPCHK(ctx, newton_prepare(ctx, only));
+        if (in_step) {
+            // captured linearisation and start; then as many cycles as this
+            // Newton step took in the previous solve before the state is read
+            // (cycles of a converged grain do nothing on the device)
+            TRY(run_phase(ctx, it == 0 ? G_NEWTON : G_NEWTON_NEXT, [&] {
+                (void)newton_prepare(ctx, -1, it == 0);
+                (void)mg_begin(ctx, tol, -1, true);
+            }));
+            const int pred = it < (int)ctx->newton_pred.size() ? std::min(ctx->newton_pred[it], max_cycles) : 0;
+            for (int k = 0; k < pred; ++k) TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+            TRY(read_batch(ctx, b));
+            if (b.nan) break;
+            if (b.pending == 0 && b.max_cycles == 0) {   // the step started converged
+                converged = true;
+                break;
+            }
+            while (b.pending > 0 && b.max_cycles < max_cycles) {
+                TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+                TRY(read_batch(ctx, b));
+            }
+            if ((int)ctx->newton_pred.size() <= it) ctx->newton_pred.resize(it + 1, 0);
+            ctx->newton_pred[it] = b.max_cycles;
+            HIPCHK(ctx, newton_limit(ctx, -1));
+            total += b.max_cycles;
+            continue;
+        }
+        HIPCHK(ctx, newton_prepare(ctx, only, it == 0));
         HIPCHK(ctx, mg_begin(ctx, tol, only, in_step));
         TRY(read_batch(ctx, b));
         if (b.nan) break;
@@ -261,8 +287,7 @@ int solve_newton(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int o
         int launched = 0;
         double last = HUGE_VAL;
         while (b.pending > 0 && launched < max_cycles) {
-            if (in_step) TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
-            else HIPCHK(ctx, mg_vcycle_launches(ctx, tol));
+            HIPCHK(ctx, mg_vcycle_launches(ctx, tol));
             ++launched;
             TRY(read_batch(ctx, b));
             if (to_floor) {

@@ -220,7 +220,7 @@ struct TimerPair { hipEvent_t a, b; int kind; };
 // (88^2 doubles and the pivot scratch stay within 64 KiB)
 constexpr int BOLTZ_INV_MAX = 88;
 constexpr int SORT_LEVELS = 5;   // a slow species is sorted up to 16x less often
-enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_SORT, G_COUNT = G_SORT + SORT_LEVELS };
+enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_NEWTON, G_NEWTON_NEXT, G_SORT, G_COUNT = G_SORT + SORT_LEVELS };
 
 }  // namespace apic
 
@@ -256,6 +256,8 @@ struct apic_ctx {
     int max_nodes = 0, max_n1 = 0, max_n2 = 0;
     bool x2_transposed = false;             // finest-level x2 sweeps on transposed copies
     int pred_cycles = 0;                    // cycles of the previous in-step solve
+    std::vector<int> newton_pred;           // Boltzmann electrons: cycles of each Newton step
+                                            // of the previous in-step solve
     // schedule and graphs
     apic::Schedule sched;
     bool tuned = false;
@@ -301,7 +303,7 @@ hipError_t launch_set_boundary(apic_ctx* ctx);
 
 // multigrid.hip
 hipError_t mg_extrapolate(apic_ctx* ctx);
-hipError_t newton_prepare(apic_ctx* ctx, int only);
+hipError_t newton_prepare(apic_ctx* ctx, int only, bool invert);
 hipError_t newton_limit(apic_ctx* ctx, int only);
 hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step);
 hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol);

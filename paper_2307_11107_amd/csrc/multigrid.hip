@@ -1133,7 +1133,7 @@ k_restrict_shift(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coa
 // assembled in LDS and inverted in place by Gauss-Jordan elimination with
 // partial pivoting (the row interchanges are undone on the columns of the
 // inverse at the end), then written with rows padded to an even length.
-constexpr int INV_BLOCK = 256;
+constexpr int INV_BLOCK = 1024;   // sixteen waves, each taking whole rows
 
 template <class ST>
 __global__ void __launch_bounds__(INV_BLOCK)
@@ -1214,10 +1214,11 @@ k_coarse_invert(const MGDesc* __restrict__ lv, int only) {
         for (int c = threadIdx.x; c < m; c += INV_BLOCK)
             M[(size_t)k * m + c] = (c == k ? 1.0 : M[(size_t)k * m + c]) * pinv;
         __syncthreads();
-        for (int t = threadIdx.x; t < m * m; t += INV_BLOCK) {
-            const int r = t / m, c = t - r * m;
+        for (int r = (int)threadIdx.x >> 6; r < m; r += INV_BLOCK / 64) {
             if (r == k) continue;
-            M[t] = (c == k ? 0.0 : M[t]) - M[(size_t)k * m + c] * colk[r];
+            const double fr = colk[r];
+            double* row = M + (size_t)r * m;
+            for (int c = threadIdx.x & 63; c < m; c += 64) row[c] = (c == k ? 0.0 : row[c]) - M[(size_t)k * m + c] * fr;
         }
         __syncthreads();
     }
@@ -1234,10 +1235,8 @@ k_coarse_invert(const MGDesc* __restrict__ lv, int only) {
     }
     const int mp = (m + 1) & ~1;
     double* inv = const_cast<double*>(D.inv);
-    for (int t = threadIdx.x; t < m * mp; t += INV_BLOCK) {
-        const int r = t / mp, c = t - r * mp;
-        gbl(inv)[t] = c < m ? M[(size_t)r * m + c] : 0.0;
-    }
+    for (int r = (int)threadIdx.x >> 6; r < m; r += INV_BLOCK / 64)
+        for (int c = threadIdx.x & 63; c < mp; c += 64) gbl(inv)[(size_t)r * mp + c] = c < m ? M[(size_t)r * m + c] : 0.0;
 }
 
 // Damped Newton: a step changes phi by at most NEWTON_MAX_STEP (Te/e) at any
@@ -1266,9 +1265,11 @@ hipError_t newton_limit(apic_ctx* ctx, int only) {
     return hipGetLastError();
 }
 
-// The Newton linearisation about the current phi on every level, and the
-// coarsest inverses.
-hipError_t newton_prepare(apic_ctx* ctx, int only) {
+// The Newton linearisation about the current phi on every level, and (invert)
+// the coarsest inverses.  A solve forms them on its first Newton step only:
+// later steps change E little, and an inexact coarsest operator only slows the
+// cycles' convergence to the same fine-level solution.
+hipError_t newton_prepare(apic_ctx* ctx, int only, bool invert) {
     const int G = (int)ctx->grains.size();
     const int nl = ctx->n_levels;
     hipLaunchKernelGGL(k_newton_prepare, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->gdesc,
@@ -1278,7 +1279,7 @@ hipError_t newton_prepare(apic_ctx* ctx, int only) {
         hipLaunchKernelGGL(k_restrict_shift, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G), dim3(MG_BLOCK), 0,
                            ctx->stream, ctx->mgdesc + (size_t)l * G, ctx->mgdesc + (size_t)(l + 1) * G, only);
     }
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l < nl && invert; ++l) {
         const int m = ctx->lvl_max_m[l];
         if (m <= 0) continue;
         const size_t lds = sizeof(double) * (size_t)m * m;
