@@ -78,6 +78,29 @@ def node_volumes(grid, order=12):
     return vol
 
 
+def node_loads(grid, fun, order=8):
+    """integral over the support of hat_ij of fun(x1, x2) dOmega, [i2, i1]
+    (Gauss-Legendre, order^2 points per cell)."""
+    gx, gw = np.polynomial.legendre.leggauss(order)
+    u = 0.5 * (gx + 1.0)
+    w = 0.5 * gw
+    h1, h2 = grid.h1, grid.h2
+    i = np.arange(grid.n1)
+    U = u[None, :, None]
+    Vv = u[None, None, :]
+    W = (w[:, None] * w[None, :])[None, :, :] * h1 * h2
+    x1 = -1.0 + (i[:, None, None] + U) * h1
+    out = np.zeros(grid.shape)
+    for j in range(grid.n2):
+        x2 = -1.0 + (j + Vv) * h2 + 0.0 * x1
+        f = geo.dOmega_dx1dx2(x1, x2, grid.alpha) * fun(x1 + 0.0 * x2, x2) * W
+        out[j, :-1] += np.sum(f * (1 - U) * (1 - Vv), axis=(1, 2))
+        out[j, 1:] += np.sum(f * U * (1 - Vv), axis=(1, 2))
+        out[j + 1, :-1] += np.sum(f * (1 - U) * Vv, axis=(1, 2))
+        out[j + 1, 1:] += np.sum(f * U * Vv, axis=(1, 2))
+    return out
+
+
 def domain_volume(grid, order=12):
     """Integral of dOmega over the whole domain (sum of the node volumes)."""
     return float(np.sum(node_volumes(grid, order)))

@@ -13,6 +13,8 @@ leaving through the outer boundary are removed; a Maxwellian flux is injected
 through the outer boundary.  Diagnostics: the electric force on the grain from
 the surface field, and the surface charge density from the normal field.
 
+With Config.conservative the field solve uses the conservative (finite-element)
+form of poisson.assemble_fe, its right-hand side the node charges.
 With Config.boltzmann the electrons are not moved: their density is n0 exp(phi)
 (Section 2, last paragraph; the physical sign) and the field solve is the
 nonlinear one of poisson.solve_boltzmann, started from the current potential.
@@ -86,6 +88,7 @@ class Config:
     grain: int = 0
     species: list = dc_field(default_factory=list)
     boltzmann: bool = False       # electrons as n0 exp(phi), not moved (species: the moved ones)
+    conservative: bool = False    # field solve on the conservative (finite-element) form
 
 
 def _max_sampled(f, npts=4097):
@@ -137,7 +140,12 @@ class Simulation:
         self.diag_steps = 0
         self.phi = self.phi1 = self.phi2 = None
         if vacuum_field:
-            self.set_phi(self.solver.solve(np.zeros(self.grid.shape), cfg.phi_grain, cfg.phi_out))
+            if cfg.conservative:
+                self._A = poisson.assemble_fe(self.grid)
+                self.set_phi(poisson.solve_fe(self.grid, self._A, np.zeros(self.grid.shape), cfg.kappa,
+                                              cfg.phi_grain, cfg.phi_out))
+            else:
+                self.set_phi(self.solver.solve(np.zeros(self.grid.shape), cfg.phi_grain, cfg.phi_out))
 
     @property
     def solver(self):
@@ -221,6 +229,15 @@ class Simulation:
         return [self.w[s] * deps[s] / self.vol for s in range(len(deps))]
 
     def solve_field(self, deps):
+        if self.cfg.conservative:
+            # the node charges themselves are the right-hand side
+            if self._A is None:
+                self._A = poisson.assemble_fe(self.grid)
+            charge = sum(self.cfg.species[s].q * self.w[s] * d for s, d in enumerate(deps))
+            self.phi = poisson.solve_fe(self.grid, self._A, charge, self.cfg.kappa, self.cfg.phi_grain,
+                                        self.cfg.phi_out)
+            self.phi1, self.phi2 = field.nodal_gradient(self.phi, self.grid)
+            return
         rho = sum(self.cfg.species[s].q * n for s, n in enumerate(self.densities(deps)))
         if self.cfg.boltzmann:
             # Boltzmann electrons: Newton from the current potential

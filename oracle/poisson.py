@@ -19,6 +19,15 @@ Readings (the paper does not spell these out):
     vanish (they carry 1 - x2^2), so the row keeps the d2/dx1^2 term and the
     d/dx2 term, the latter by the second-order one-sided difference
     (+-3 phi_j -+ 4 phi_{j-+1} +- phi_{j-+2}) / (2 h2).
+Conservative form (an alternative to eq. 7's expanded operator, selected by
+the caller): the Laplacian written as a divergence in (x1, x2), discretised by
+bilinear finite elements -- S_ab = -integral of grad N_a . grad N_b dOmega with
+the metric g^ij = grad x_i . grad x_j of eqs. (2), (7) and the volume element
+of eq. (5), 2 x 2 Gauss points per cell (assemble_fe).  S is symmetric, its
+full rows sum to zero (the bilinear hats sum to one), and its right-hand side
+is the charge of the node, -(1/kappa^2) integral of rho N_a dOmega: Gauss's law
+holds exactly between the plasma's node charges and the boundary rows.
+
 Boltzmann electrons (Section 2, last paragraph: the electrons are not moved,
 their density follows the Boltzmann relation instead): with n_e = n0 exp(phi)
 in these units (phi in Te/e, n0 = 1; the physical sign, electrons gather where
@@ -158,3 +167,66 @@ def solve_boltzmann(grid, A, rho_p, kappa, phi_grain, phi_out, phi0=None, tol=1e
         if np.max(np.abs(d)) <= tol * max(np.max(np.abs(phi)), 1.0):
             return phi.reshape(grid.shape), it
     raise RuntimeError("Newton did not converge")
+
+
+def assemble_fe(grid, full=False):
+    """Bilinear finite-element matrix of the conservative form (module doc):
+    S_ab = -sum over cells of sum over 2 x 2 Gauss points w J g^ij dN_a/dx_i
+    dN_b/dx_j, J = dOmega/dx1dx2 (eq. 5), g11 = c11, g22 = c22, g12 = c12 / 2 of
+    eq. (7).  With full=False the Dirichlet rows (i1 = 0, n1) are identity rows,
+    as in assemble; with full=True every row is the element sum."""
+    n1, n2 = grid.n1, grid.n2
+    h1, h2 = grid.h1, grid.h2
+    nx = n1 + 1
+    g = 0.5 / np.sqrt(3.0)
+    pts = (0.5 - g, 0.5 + g)
+    I, J = np.meshgrid(np.arange(n1), np.arange(n2), indexing="xy")   # [j, i] cells
+    K = {}
+    for u in pts:
+        for v in pts:
+            x1 = -1.0 + (I + u) * h1
+            x2 = -1.0 + (J + v) * h2
+            jac = geo.dOmega_dx1dx2(x1, x2, grid.alpha) * 0.25 * h1 * h2
+            c11, c22, c12, _ = geo.laplace_coeffs(x1, x2, grid.alpha)
+            # local corners (di, dj): N = (u or 1-u)(v or 1-v)
+            grads = {}
+            for di in (0, 1):
+                for dj in (0, 1):
+                    fu = u if di else 1.0 - u
+                    fv = v if dj else 1.0 - v
+                    grads[(di, dj)] = ((1.0 if di else -1.0) * fv / h1, fu * (1.0 if dj else -1.0) / h2)
+            for a, (a1, a2) in grads.items():
+                for b, (b1, b2) in grads.items():
+                    val = jac * (c11 * a1 * b1 + 0.5 * c12 * (a1 * b2 + a2 * b1) + c22 * a2 * b2)
+                    K[(a, b)] = K.get((a, b), 0.0) - val
+    rows, cols, vals = [], [], []
+    for (a, b), val in K.items():
+        ra = (J + a[1]) * nx + (I + a[0])
+        cb = (J + b[1]) * nx + (I + b[0])
+        rows.append(ra.ravel())
+        cols.append(cb.ravel())
+        vals.append(val.ravel())
+    nn = nx * (n2 + 1)
+    S = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nn, nn))
+    if full:
+        return S
+    dirichlet = np.zeros(nn, dtype=bool)
+    dirichlet[0::nx] = True
+    dirichlet[n1::nx] = True
+    keep = sp.diags((~dirichlet).astype(np.float64))
+    return (keep @ S + sp.diags(dirichlet.astype(np.float64))).tocsr()
+
+
+def solve_fe(grid, S, charge, kappa, phi_grain, phi_out):
+    """Solve of the conservative form: S phi = -(1/kappa^2) charge on the
+    unknown nodes (charge = integral of rho N_a dOmega, [i2, i1]), the boundary
+    potentials on the Dirichlet rows; sparse LU with two refinement steps."""
+    nx = grid.n1 + 1
+    b = -np.asarray(charge, dtype=np.float64).ravel() / kappa ** 2
+    b[0::nx] = phi_grain
+    b[grid.n1::nx] = phi_out
+    lu = spla.splu(S.tocsc())
+    x = lu.solve(b)
+    for _ in range(2):
+        x = x + lu.solve(b - S @ x)
+    return x.reshape(grid.shape)
