@@ -75,7 +75,7 @@ def grain_cfgs(grains, boltzmann=False):
     return cfgs
 
 
-def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=False):
+def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=False, conservative=False):
     """Loads every grain, runs `warmup` steps (the autotuner's steps among
     them), then times `steps` steps between device synchronisations."""
     import torch
@@ -83,7 +83,8 @@ def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=
     prec = apic.APIC_FP32_SPLIT if precision == "fp32" else apic.APIC_FP64
     ns = 1 if boltzmann else 2
     ctx = apic.apic_init(grain_cfgs(grains, boltzmann), apic.opts(precision=prec, inject=True, stream=stream,
-                                                                  autotune=autotune, boltzmann_electrons=boltzmann))
+                                                                  autotune=autotune, boltzmann_electrons=boltzmann,
+                                                                  conservative_poisson=conservative))
     try:
         for g in range(len(grains)):
             for s in range(ns):
@@ -145,6 +146,7 @@ def main():
     ap.add_argument("--ensemble-warmup", type=int, default=30)
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-boltzmann", action="store_true")
+    ap.add_argument("--no-conservative", action="store_true")
     ap.add_argument("--c5-steps", type=int, default=20)
     ap.add_argument("--c5-warmup", type=int, default=6)
     args = ap.parse_args()
@@ -255,6 +257,18 @@ def main():
                                       for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
             "mg_cycles_per_step": tb["mg_cycles"] / max(tb["steps"], 1),
             "balance_exact": rb["balance_exact"]}
+    if not args.no_conservative:
+        # the same workload with the conservative (finite-element) field solve
+        rc = run_gpu([w], "fp32", args.steps, args.warmup, stream, conservative=True)
+        tc = rc["timing"]
+        out["conservative_poisson"] = {
+            "workload": f"{args.workload}, FP32 split, field solve on the conservative (bilinear finite-element) form",
+            "value": rc["particle_steps"] / rc["elapsed"], "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * rc["elapsed"] / args.steps,
+            "breakdown_ms_per_step": {k: tc[k] / max(tc["steps"], 1)
+                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+            "mg_cycles_per_step": tc["mg_cycles"] / max(tc["steps"], 1),
+            "balance_exact": rc["balance_exact"]}
     if not args.no_cpu_baseline:
         rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",

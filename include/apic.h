@@ -100,6 +100,13 @@ typedef struct {
                                     then list the moved species only.  The grid must
                                     coarsen (halving both cell counts) to <= 88 nodes,
                                     else APIC_ERANGE                                      */
+    int32_t conservative_poisson; /* 1: eq. (6) with the Laplacian in conservative form,
+                                    discretised by bilinear finite elements (symmetric;
+                                    the right-hand side is each node's deposited charge,
+                                    so Gauss's law holds exactly) instead of the expanded
+                                    9-point operator of eq. (7); apic_solve_poisson's rho
+                                    is then weighted by the node volumes.  Not with
+                                    boltzmann_electrons (APIC_EINVAL)                      */
 } apic_opts;
 
 /* Grain tallies (Sections 1-2: currents, drag, torque and heat flux follow from

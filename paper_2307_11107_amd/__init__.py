@@ -59,9 +59,11 @@ def grain_cfg(alpha, n1, n2, species_list, x1_out=-0.1, wce=0.0, kappa=1.0, phi_
 
 
 def opts(precision=APIC_FP32_SPLIT, inject=True, frozen_field=False, sort_every=0,
-         poisson_tol=0.0, poisson_max_cycles=0, stream=None, autotune=False, boltzmann_electrons=False):
+         poisson_tol=0.0, poisson_max_cycles=0, stream=None, autotune=False, boltzmann_electrons=False,
+         conservative_poisson=False):
     o = apic_opts()
     o.boltzmann_electrons = int(boltzmann_electrons)
+    o.conservative_poisson = int(conservative_poisson)
     o.precision, o.inject, o.frozen_field, o.sort_every = precision, int(inject), int(frozen_field), sort_every
     o.poisson_tol, o.poisson_max_cycles = poisson_tol, poisson_max_cycles
     o.autotune = int(autotune)

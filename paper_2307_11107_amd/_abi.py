@@ -28,7 +28,7 @@ class apic_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("inject", C.c_int32), ("frozen_field", C.c_int32),
                 ("sort_every", C.c_int32), ("poisson_tol", C.c_double),
                 ("poisson_max_cycles", C.c_int32), ("autotune", C.c_int32), ("stream", C.c_void_p),
-                ("boltzmann_electrons", C.c_int32)]
+                ("boltzmann_electrons", C.c_int32), ("conservative_poisson", C.c_int32)]
 
 
 class apic_tally(C.Structure):

@@ -444,6 +444,7 @@ struct HostSetup {
     int max_dense = 600;        // largest level solved by the dense inverse
     int threads = 1;            // host threads for the inverse
     bool boltzmann = false;     // Newton term on every level: the coarsest inverse is formed on the device
+    bool fe = false;            // conservative (finite-element) form on the finest level
     int rc = APIC_OK;
     std::string err;
 };
@@ -537,7 +538,8 @@ void host_setup(Grain& g, const apic_grain_cfg& c, int gi, HostSetup& hs) {
     // iterated on the FP64 residual, while on a correction level it is exact
     // enough.
     hs.levels.resize(1);
-    fine_stencil(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
+    if (hs.fe) fine_stencil_fe(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
+    else fine_stencil(n1, n2, c.x1_out, c.alpha, hs.levels[0]);
     const int fine_dense = std::min(600, hs.max_dense);
     while ((hs.levels.back().n1 + 1) * (hs.levels.back().n2 + 1) > (hs.levels.size() == 1 ? fine_dense : hs.max_dense) &&
            hs.levels.back().n1 % 2 == 0 &&
@@ -626,7 +628,7 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             HIPCHK(ctx, launch_fill(ctx, L.shift, sizeof(double) * L.nodes));
             if (l == 0) TRY(alloc_t(ctx, &L.uold, (size_t)L.nodes));
         }
-        if (l == 0) {
+        if (l == 0 && !hs.fe) {
             // the finest operator is evaluated at the nodes; its x2 sweeps may
             // use transposed copies of u and f
             TRY(alloc_t(ctx, &L.uT, (size_t)L.nodes));
@@ -634,6 +636,7 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             TRY(alloc_t(ctx, &L.uprev, (size_t)L.nodes));
             continue;
         }
+        if (l == 0) TRY(alloc_t(ctx, &L.uprev, (size_t)L.nodes));   // the stored finest level
         TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
         stage.resize((size_t)ST_COUNT * L.nodes);
         for (int k = 0; k < ST_COUNT; ++k)
@@ -744,6 +747,7 @@ int build_tables(apic_ctx* ctx) {
         d.rhs_scale = -1.0 / (g.gp.kappa * g.gp.kappa);
         d.phi_grain = g.cfg.phi_grain;
         d.phi_out = g.cfg.phi_out;
+        d.fe = ctx->opts.conservative_poisson != 0;
         for (int s = 0; s < g.ns; ++s) {
             d.cw[s] = g.sp[s].q * g.sp[s].w;
             d.dep[s] = g.dep[s];
@@ -764,7 +768,8 @@ int build_tables(apic_ctx* ctx) {
     // sweeps on transposed copies
     size_t fine_bytes = 0;
     for (auto& g : ctx->grains) fine_bytes += 16 * (size_t)g.nodes;
-    ctx->x2_transposed = fine_bytes > ((size_t)16 << 20);
+    // (the conservative form's finest level is stored: no transposed sweeps)
+    ctx->x2_transposed = fine_bytes > ((size_t)16 << 20) && !ctx->opts.conservative_poisson;
     TRY(alloc_t(ctx, &ctx->gdesc, (size_t)G));
     HIPCHK(ctx, hipMemcpy(ctx->gdesc, ctx->gdesc_h.data(), sizeof(GrainDesc) * G, hipMemcpyHostToDevice));
 
@@ -1086,6 +1091,10 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         delete ctx;
         return fail(nullptr, APIC_EINVAL, "precision must be APIC_FP32_SPLIT or APIC_FP64");
     }
+    if (ctx->opts.boltzmann_electrons && ctx->opts.conservative_poisson) {
+        delete ctx;
+        return fail(nullptr, APIC_EINVAL, "conservative_poisson is not available with boltzmann_electrons");
+    }
     if (ctx->opts.sort_every > 0) ctx->sched.sort_every = ctx->opts.sort_every;
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -1123,6 +1132,7 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         const int nt = std::min(n_grains, hw);
         for (auto& h : hs) {
             h.boltzmann = ctx->opts.boltzmann_electrons != 0;
+            h.fe = ctx->opts.conservative_poisson != 0;
             h.max_dense = h.boltzmann ? BOLTZ_INV_MAX : dense_limit(n_grains);
             h.threads = std::max(1, hw / nt);
         }

@@ -105,6 +105,7 @@ struct GrainDesc {
     int n1, n2, nx, nodes, ns;
     double inv_h1, inv_h2, h2, alpha, rhs_scale;    // rhs_scale = -1 / kappa^2
     double phi_grain, phi_out;
+    int fe;                                         // conservative form: f from node charges
     double cw[APIC_MAX_SPECIES];                    // q w per species
     double bnd2;                                    // |A_ib u_b|^2 (row-scaled), constant
     const void* dep[APIC_MAX_SPECIES];

@@ -51,7 +51,8 @@ hipError_t launch_clear_deposits(apic_ctx* ctx) {
 }
 
 // rho = sum_s q_s w_s dep_s / V_node (units e n0); f = -(1/kappa^2) rho at the
-// unknown nodes (eq. 6 normalised), 0 on the Dirichlet columns
+// unknown nodes (eq. 6 normalised), 0 on the Dirichlet columns; in the
+// conservative form f = -(1/kappa^2) times the node's charge (rho V_node)
 template <typename D>
 __global__ void __launch_bounds__(FB)
 k_rho_rhs(const GrainDesc* __restrict__ gd) {
@@ -63,7 +64,7 @@ k_rho_rhs(const GrainDesc* __restrict__ gd) {
     const double rho = q / gbl(G.vol)[i];
     gbl(G.rho)[i] = rho;
     const int i1 = i % G.nx;
-    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * rho;
+    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * (G.fe ? q : rho);
 }
 
 hipError_t launch_rho_rhs(apic_ctx* ctx) {
@@ -81,7 +82,8 @@ k_rhs(const GrainDesc* __restrict__ gd, int grain) {
     const int i = blockIdx.x * FB + threadIdx.x;
     if (i >= G.nodes) return;
     const int i1 = i % G.nx;
-    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * gbl(G.rho)[i];
+    const double rho = gbl(G.rho)[i];
+    gbl(G.f)[i] = (i1 == 0 || i1 == G.n1) ? 0.0 : G.rhs_scale * (G.fe ? rho * gbl(G.vol)[i] : rho);
 }
 
 hipError_t launch_rhs_from_rho(apic_ctx* ctx, int grain) {

@@ -183,6 +183,57 @@ void fine_stencil(int n1, int n2, double x1_out, double a, Stencil& s) {
 }
 
 // A_c = (P^T / 4) A_f P on the unknowns; P bilinear, zero on Dirichlet columns.
+// Conservative form: bilinear finite elements, S_ab = -integral of grad N_a .
+// grad N_b dOmega with the metric of eqs. (2), (7) and the volume element of
+// eq. (5), 2 x 2 Gauss points per cell.  Symmetric; the rows of the unknown
+// nodes (1 <= i1 <= n1 - 1) are filled, as for the expanded operator.
+void fine_stencil_fe(int n1, int n2, double x1_out, double a, Stencil& s) {
+    const int nx = n1 + 1;
+    const size_t nodes = (size_t)nx * (n2 + 1);
+    s.n1 = n1;
+    s.n2 = n2;
+    for (auto& v : s.c) v.assign(nodes, 0.0);
+    s.nn.clear();
+    s.ss.clear();
+    const double h1 = (1.0 + x1_out) / n1, h2 = 2.0 / n2;
+    const double g = 0.5 / std::sqrt(3.0);
+    const double pts[2] = {0.5 - g, 0.5 + g};
+    // stencil index of the offset (di, dj) of a column node from its row node
+    auto idx = [](int di, int dj) {
+        static const int T[3][3] = {{ST_SW, ST_S, ST_SE}, {ST_W, ST_C, ST_E}, {ST_NW, ST_N, ST_NE}};
+        return T[dj + 1][di + 1];
+    };
+    for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i)
+            for (double u : pts)
+                for (double v : pts) {
+                    const double x1 = -1.0 + (i + u) * h1, x2 = -1.0 + (j + v) * h2;
+                    const double r = r_at(x1, x2, a);
+                    const double s2 = 1.0 - x2 * x2;
+                    const double c11 = ((r + 2.0 * a * x2) * (r + 2.0 * a * x2) + a * a * s2) / std::pow(r, 6);
+                    const double c22 = s2 / (r * r);
+                    const double g12 = -a * s2 / std::pow(r, 4);
+                    const double jac = dOmega(x1, x2, a) * 0.25 * h1 * h2;
+                    double d1[4], d2[4];
+                    for (int k = 0; k < 4; ++k) {
+                        const int di = k & 1, dj = k >> 1;
+                        const double fu = di ? u : 1.0 - u, fv = dj ? v : 1.0 - v;
+                        d1[k] = (di ? 1.0 : -1.0) * fv / h1;
+                        d2[k] = fu * (dj ? 1.0 : -1.0) / h2;
+                    }
+                    for (int ka = 0; ka < 4; ++ka) {
+                        const int ia = i + (ka & 1), ja = j + (ka >> 1);
+                        if (ia == 0 || ia == n1) continue;
+                        const size_t o = (size_t)ja * nx + ia;
+                        for (int kb = 0; kb < 4; ++kb) {
+                            const double val = jac * (c11 * d1[ka] * d1[kb] + g12 * (d1[ka] * d2[kb] + d2[ka] * d1[kb]) +
+                                                      c22 * d2[ka] * d2[kb]);
+                            s.c[idx((kb & 1) - (ka & 1), (kb >> 1) - (ka >> 1))][o] -= val;
+                        }
+                    }
+                }
+}
+
 void galerkin_coarse(const Stencil& f, Stencil& c) {
     const int n1f = f.n1, n2f = f.n2, nxf = n1f + 1;
     const int n1c = n1f / 2, n2c = n2f / 2, nxc = n1c + 1;

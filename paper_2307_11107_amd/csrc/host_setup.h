@@ -22,6 +22,7 @@ double bound_volume_marginal(double x1_out, double alpha);
 double bound_outer_area_density(double x1_out, double alpha);
 double grain_max_radius(double alpha);
 void fine_stencil(int n1, int n2, double x1_out, double alpha, Stencil& s);
+void fine_stencil_fe(int n1, int n2, double x1_out, double alpha, Stencil& s);
 void galerkin_coarse(const Stencil& fine, Stencil& coarse);
 void dense_matrix(const Stencil& s, std::vector<double>& A);
 bool invert(std::vector<double> A, int m, std::vector<double>& inv, int threads);

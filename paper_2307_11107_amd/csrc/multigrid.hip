@@ -583,6 +583,7 @@ __device__ inline double sum_parts(const double* __restrict__ p, int nb) {
 // and the row-scaled norm weighs every node alike.  One partial sum per
 // workgroup, part[grain][block]; the batch counters of the check that follows
 // are cleared here.
+template <class ST>
 __global__ void __launch_bounds__(MG_BLOCK)
 k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part,
                 MGBatch* __restrict__ mb) {
@@ -597,7 +598,7 @@ k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, d
         const int n1 = D.n1, n2 = D.n2, nx = n1 + 1;
         const int j = idx / nx, i = idx - j * nx;
         if (i > 0 && i < n1) {
-            const FineStencil st(D);
+            const ST st(D);
             const Coef k = st.at(j, i, idx);
             const gptr<const double> u = gbl(static_cast<const double*>(D.u));
             double au = k.C * u[idx] + k.W * u[idx - 1] + k.E * u[idx + 1];
@@ -647,6 +648,7 @@ k_mg_sum_check(MGState* __restrict__ ms, const GrainDesc* __restrict__ gd, int n
     }
 }
 // |D^-1 f|^2 over the unknown nodes, partial sums as above
+template <class ST>
 __global__ void __launch_bounds__(MG_BLOCK)
 k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part) {
     const MGDesc& D = lv[blockIdx.y];
@@ -661,7 +663,7 @@ k_rhs_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double
     if (idx < D.nodes) {
         const int i = idx % nx;
         if (i > 0 && i < D.n1) {
-            const FineStencil st(D);
+            const ST st(D);
             const double q = gbl(D.f)[idx] / st.diag(idx / nx, i, idx);
             v = q * q;
         }
@@ -1018,7 +1020,7 @@ static void smooth_st(apic_ctx* ctx, int l) {
 }
 
 static void smooth(apic_ctx* ctx, int l) {
-    if (l > 0) {
+    if (l > 0 || ctx->opts.conservative_poisson) {   // stored operator
         smooth_st<StoredStencil>(ctx, l);
         return;
     }
@@ -1050,8 +1052,12 @@ static int norm_blocks(apic_ctx* ctx) { return (ctx->lvl_max_nodes[0] + MG_BLOCK
 static void residual_check(apic_ctx* ctx, double tol, int count_cycle, bool with_b) {
     const int G = (int)ctx->grains.size();
     const int nb = norm_blocks(ctx);
-    hipLaunchKernelGGL(k_residual_norm, dim3(nb, G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgs,
-                       ctx->norm_part, ctx->mgb);
+    if (ctx->opts.conservative_poisson)
+        hipLaunchKernelGGL(k_residual_norm<StoredStencil>, dim3(nb, G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
+                           ctx->mgs, ctx->norm_part, ctx->mgb);
+    else
+        hipLaunchKernelGGL(k_residual_norm<FineStencil>, dim3(nb, G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
+                           ctx->mgs, ctx->norm_part, ctx->mgb);
     hipLaunchKernelGGL(k_mg_sum_check, dim3(G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, ctx->gdesc, nb,
                        ctx->norm_part, with_b ? ctx->norm_part + (size_t)G * nb : nullptr, tol * tol, count_cycle,
                        ctx->mgb);
@@ -1063,8 +1069,12 @@ static void residual_check(apic_ctx* ctx, double tol, int count_cycle, bool with
 hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step) {
     const int G = (int)ctx->grains.size();
     hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgs, G, only_grain, (int)in_step);
-    hipLaunchKernelGGL(k_rhs_norm, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc,
-                       ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
+    if (ctx->opts.conservative_poisson)
+        hipLaunchKernelGGL(k_rhs_norm<StoredStencil>, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream,
+                           ctx->mgdesc, ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
+    else
+        hipLaunchKernelGGL(k_rhs_norm<FineStencil>, dim3(norm_blocks(ctx), G), dim3(MG_BLOCK), 0, ctx->stream,
+                           ctx->mgdesc, ctx->mgs, ctx->norm_part + (size_t)G * norm_blocks(ctx));
     residual_check(ctx, tol, 0, true);
     if (ctx->x2_transposed) transpose<2>(ctx);
     return hipGetLastError();
@@ -1308,7 +1318,10 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
     coarse_solve(ctx, 0);
     for (int l = 0; l + 1 < nl; ++l) {
         const int cn = ctx->lvl_max_nodes[l + 1];
-        if (l == 0)
+        if (l == 0 && ctx->opts.conservative_poisson)
+            hipLaunchKernelGGL(k_restrict_residual<StoredStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
+                               dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
+        else if (l == 0)
             hipLaunchKernelGGL(k_restrict_residual<FineStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
         else  // level l's u was cleared by the restriction into it

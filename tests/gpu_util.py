@@ -20,7 +20,8 @@ def species_pair(w, electrons=True, ions=True, weight=0.0, n_macro=None):
 
 
 def make_pair(w, precision, inject=True, frozen=False, electrons=True, ions=True, weight=0.0,
-              n_macro=None, n_bins=0, sort_every=0, poisson_tol=0.0, capacity=0, boltzmann=False):
+              n_macro=None, n_bins=0, sort_every=0, poisson_tol=0.0, capacity=0, boltzmann=False,
+              conservative=False):
     dev_sp, ora_sp = species_pair(w, electrons, ions, weight, n_macro)
     if capacity:
         for s in dev_sp:
@@ -30,10 +31,10 @@ def make_pair(w, precision, inject=True, frozen=False, electrons=True, ions=True
                          seed=w["seed"])
     ctx = apic.apic_init([cfg], apic.opts(precision=precision, inject=inject, frozen_field=frozen,
                                           sort_every=sort_every, poisson_tol=poisson_tol,
-                                          boltzmann_electrons=boltzmann))
+                                          boltzmann_electrons=boltzmann, conservative_poisson=conservative))
     ocfg = Config(alpha=w["alpha"], n1=w["n1"], n2=w["n2"], x1_out=w["x1_out"], wce=w["wce"],
                   kappa=w["kappa"], dt=w["dt"], n_bins=n_bins, seed=w["seed"], species=ora_sp,
-                  boltzmann=boltzmann)
+                  boltzmann=boltzmann, conservative=conservative)
     sim = Simulation(ocfg)
     sim.inject_enabled = inject
     sim.frozen = frozen
