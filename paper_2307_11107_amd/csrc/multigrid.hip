@@ -875,8 +875,9 @@ k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
 }
 
 // ------------------------------------------------------------------ launches
-// Line-solve launches.  A line of L unknowns gets NT = 512 threads when it is
-// long (fewer equations per thread, shorter PCR critical path), else 256; the
+// Line-solve launches.  An x1 line gets 1024 threads beyond 512 unknowns, else
+// 256, an x2 line 512 beyond 256, else 256 (fewer equations per thread, a
+// shorter PCR critical path); the
 // x2 sweeps group LPB neighbouring lines of one colour per workgroup while
 // that still leaves at least two workgroups per compute unit.
 static int round8(int x) { return (x + 7) / 8 * 8; }
@@ -952,7 +953,7 @@ static void sweep_x1(apic_ctx* ctx, int l, bool prolong) {
     }
     for (int color = 0; color < colors; ++color) {
         const bool pro = prolong && color == 0;
-        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<512, ST>(ctx, l, color, pro);
+        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<1024, ST>(ctx, l, color, pro);
         else relax_x1_k<256, ST>(ctx, l, color, pro);
     }
 }
