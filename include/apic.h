@@ -193,7 +193,12 @@ int apic_step(apic_ctx* ctx, int64_t n_steps);
  * is the charge density sum_s q_s n_s at the nodes; NULL: deposit the current
  * particles.  The solution becomes the grain's field for the following steps.
  * phi_out (host, may be NULL) receives phi.  Iterates multigrid cycles to the
- * round-off floor (row-scaled relative residual <= 1e-15, or stagnation). */
+ * round-off floor (row-scaled relative residual <= 1e-15, or stagnation).
+ * With boltzmann_electrons, rho is the charge density of the moved species and
+ * the electrons' n0 exp(phi) is added by Newton's method (to the round-off
+ * floor of the nonlinear residual; APIC_EDEVICE if it does not converge); with
+ * conservative_poisson, rho is weighted by the node volumes to the node
+ * charges of the finite-element form. */
 int apic_solve_poisson(apic_ctx* ctx, int32_t grain, const double* rho, double* phi_out);
 
 /* Copies the grain's tallies to the host (synchronises the stream). */
