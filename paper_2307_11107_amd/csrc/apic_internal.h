@@ -23,7 +23,7 @@
 namespace apic {
 
 constexpr int INJ_BLOCK = 256;                  // threads per injection workgroup
-constexpr int INJ_PER_BLOCK = 16 * INJ_BLOCK;   // particles per injection workgroup
+constexpr int INJ_PER_BLOCK = 4 * INJ_BLOCK;    // particles per injection workgroup
 
 // Per-species parameters seen by the kernels.
 struct SpeciesParams {
