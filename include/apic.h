@@ -216,6 +216,14 @@ int apic_particles(apic_ctx* ctx, int32_t grain, int32_t species, int64_t cap,
  * deposit (host arrays of (n1+1)(n2+1); either may be NULL). */
 int apic_fields(apic_ctx* ctx, int32_t grain, double* phi, double* rho);
 
+/* Normal electric field on the grain surface from the current potential
+ * (Section 2: the field on the conducting surface gives its surface charge):
+ * E_n = -|grad x1| dphi/dx1 at the grain nodes i2 = 0..n2 (host array of n2+1,
+ * units Te/(e R0), the one-sided second-order derivative on x1 = -1).  The
+ * surface charge density is eps0 E_n; the grain's electric force, summed per
+ * step in apic_tallies' F_el_sum, integrates E_n^2/2 n_Z over the surface. */
+int apic_surface_field(apic_ctx* ctx, int32_t grain, double* E_n);
+
 /* Enables (1) or disables (0) HIP-event timing of the kernels, resetting the
  * accumulated times; apic_timing synchronises and returns them. */
 int apic_set_profiling(apic_ctx* ctx, int32_t on);

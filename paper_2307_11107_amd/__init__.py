@@ -158,6 +158,13 @@ def apic_fields(ctx, grain, shape):
     return phi.reshape(shape), rho.reshape(shape)
 
 
+def apic_surface_field(ctx, grain, n2):
+    """Normal field E_n on the grain at the nodes i2 = 0..n2 (surface charge = eps0 E_n)."""
+    en = np.zeros(n2 + 1)
+    _check(lib().apic_surface_field(ctx, grain, _dptr(en)), ctx)
+    return en
+
+
 def apic_set_profiling(ctx, on=True):
     _check(lib().apic_set_profiling(ctx, int(on)), ctx)
 

@@ -66,6 +66,7 @@ PROTOTYPES = {
     "apic_particles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D, _D, _D,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "apic_fields": (C.c_int, [C.c_void_p, C.c_int32, _D, _D]),
+    "apic_surface_field": (C.c_int, [C.c_void_p, C.c_int32, _D]),
     "apic_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "apic_timing": (C.c_int, [C.c_void_p, C.POINTER(apic_kernel_times)]),
     "apic_schedule": (C.c_int, [C.c_void_p, C.POINTER(apic_sched)]),

@@ -1376,6 +1376,20 @@ int apic_particles(apic_ctx* ctx, int32_t grain, int32_t species, int64_t cap, d
     return APIC_OK;
 }
 
+int apic_surface_field(apic_ctx* ctx, int32_t grain, double* E_n) {
+    TRY(check_grain(ctx, grain));
+    if (!E_n) return fail(ctx, APIC_EINVAL, "E_n is NULL");
+    const int n = ctx->grains[grain].gp.n2 + 1;
+    double* d = nullptr;
+    TRY(alloc_t(ctx, &d, (size_t)n));
+    hipError_t e = launch_surface_field(ctx, grain, d);
+    if (e == hipSuccess) e = hipMemcpyAsync(E_n, d, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(ctx, APIC_EDEVICE, std::string("apic_surface_field: ") + hipGetErrorString(e));
+    return APIC_OK;
+}
+
 int apic_fields(apic_ctx* ctx, int32_t grain, double* phi, double* rho) {
     TRY(check_grain(ctx, grain));
     Grain& g = ctx->grains[grain];

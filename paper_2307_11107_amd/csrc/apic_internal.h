@@ -299,6 +299,7 @@ hipError_t launch_clear_deposits(apic_ctx* ctx);
 hipError_t launch_rho_rhs(apic_ctx* ctx);
 hipError_t launch_rhs_from_rho(apic_ctx* ctx, int grain);
 hipError_t launch_gradient(apic_ctx* ctx);
+hipError_t launch_surface_field(apic_ctx* ctx, int grain, double* out);
 hipError_t launch_grain_force(apic_ctx* ctx);
 hipError_t launch_set_boundary(apic_ctx* ctx);
 

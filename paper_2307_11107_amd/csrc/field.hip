@@ -140,29 +140,39 @@ hipError_t launch_gradient(apic_ctx* ctx) {
     return hipGetLastError();
 }
 
+// Normal field on the grain at node i2 = j, E_n = -|grad x1| dphi/dx1 (the
+// one-sided nodal derivative on x1 = -1); |grad x1|, n_Z = x1_Z / |grad x1| and
+// r of the node are returned too.  The surface charge density is eps0 E_n.
+__device__ inline double surface_En(const GrainDesc& G, int j, double& gn, double& nZ, double& r) {
+    const double alpha = G.alpha;
+    const double x2 = -1.0 + j * G.h2;
+    r = r_of(-1.0, x2, alpha);
+    const double s = sqrt(fmax(1.0 - x2 * x2, 0.0));
+    const Metric<double> m = metric_at(r, x2, s, alpha);
+    gn = sqrt(m.x1R * m.x1R + m.x1Z * m.x1Z);
+    nZ = m.x1Z / gn;
+    const gptr<const double> row = gbl(static_cast<const double*>(G.u) + (size_t)j * G.nx);
+    const double p1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * G.inv_h1;
+    return -gn * p1;
+}
+
 // Electric force on the grain, F_Z = integral over x1 = -1 of E_n^2 / 2 * n_Z dA
-// (Maxwell stress on a conductor), E_n = -|grad x1| dphi/dx1, trapezoid in x2;
-// one workgroup per grain.
+// (Maxwell stress on a conductor), trapezoid in x2; one workgroup per grain.
 __global__ void __launch_bounds__(FB)
 k_grain_force(const GrainDesc* __restrict__ gd) {
     __shared__ double red[FB];
     const GrainDesc& G = gd[blockIdx.x];
-    const int nx = G.nx, n2 = G.n2;
+    const int n2 = G.n2;
     const double alpha = G.alpha, h2 = G.h2;
     double sum = 0.0;
     for (int j = threadIdx.x; j <= n2; j += blockDim.x) {
         const double x2 = -1.0 + j * h2;
-        const double r = r_of(-1.0, x2, alpha);
-        const double s = sqrt(fmax(1.0 - x2 * x2, 0.0));
-        const Metric<double> m = metric_at(r, x2, s, alpha);
-        const double gn = sqrt(m.x1R * m.x1R + m.x1Z * m.x1Z);
-        const gptr<const double> row = gbl(static_cast<const double*>(G.u) + (size_t)j * nx);
-        const double p1 = (-3.0 * row[0] + 4.0 * row[1] - row[2]) * 0.5 * G.inv_h1;
-        const double En = -gn * p1;
+        double gn, nZ, r;
+        const double En = surface_En(G, j, gn, nZ, r);
         const double t = alpha / (r + 2.0 * alpha * x2);
         const double dA = 6.283185307179586 * r * r * sqrt(1.0 + (1.0 - x2 * x2) * t * t);
         const double w = (j == 0 || j == n2) ? 0.5 : 1.0;
-        sum += w * 0.5 * En * En * (m.x1Z / gn) * dA;
+        sum += w * 0.5 * En * En * nZ * dA;
     }
     red[threadIdx.x] = sum;
     __syncthreads();
@@ -171,6 +181,22 @@ k_grain_force(const GrainDesc* __restrict__ gd) {
         __syncthreads();
     }
     if (threadIdx.x == 0) gbl(&G.ctr->F_el_sum)[0] += red[0] * h2;
+}
+
+// E_n at the grain nodes of one grain (out: n2 + 1 values, device)
+__global__ void __launch_bounds__(FB)
+k_surface_field(const GrainDesc* __restrict__ gd, int grain, double* __restrict__ out) {
+    const GrainDesc& G = gd[grain];
+    const int j = blockIdx.x * FB + threadIdx.x;
+    if (j > G.n2) return;
+    double gn, nZ, r;
+    gbl(out)[j] = surface_En(G, j, gn, nZ, r);
+}
+
+hipError_t launch_surface_field(apic_ctx* ctx, int grain, double* out) {
+    const int n2 = ctx->grains[grain].gp.n2;
+    hipLaunchKernelGGL(k_surface_field, dim3((n2 + FB) / FB), dim3(FB), 0, ctx->stream, ctx->gdesc, grain, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_grain_force(apic_ctx* ctx) {

@@ -104,3 +104,28 @@ def test_in_step_solves_converge_in_few_cycles():
     per_step = tm["mg_cycles"] / tm["steps"]
     print(f"multigrid cycles per step {per_step:.2f}", flush=True)
     assert per_step <= 6.0
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.2, -0.24])
+def test_surface_field_matches_oracle(alpha):
+    """The normal field on the grain (Section 2: it gives the surface charge
+    and, through the Maxwell stress, the electric force) from the device's
+    potential against the oracle's formula on the oracle's potential."""
+    from oracle import field, geometry as geo
+    n1, n2 = 128, 96
+    rho = smooth_density(n1, n2, seed=11, amplitude=2.0)
+    ctx = _ctx(n1, n2, alpha, -0.1, 1.0)
+    try:
+        apic.apic_solve_poisson(ctx, 0, rho, shape=(n2 + 1, n1 + 1))
+        en = apic.apic_surface_field(ctx, 0, n2)
+    finally:
+        apic.apic_free(ctx)
+    g = Grid(n1, n2, -0.1, alpha)
+    phi = PoissonSolver(g).solve(source_from_density(rho, 1.0), -2.5, 0.0)
+    phi1, _ = field.nodal_gradient(phi, g)
+    x2 = g.x2_nodes()
+    x1R, x1Z, _, _ = geo.metric(np.full_like(x2, -1.0), x2, alpha)
+    ref = -np.hypot(x1R, x1Z) * phi1[:, 0]
+    err = np.max(np.abs(en - ref)) / np.max(np.abs(ref))
+    print(f"surface field alpha={alpha}: rel err {err:.2e}")
+    assert err < 1e-9
