@@ -88,3 +88,26 @@ def test_ions_only_run_matches_oracle(precision):
         assert abs(na - nb) <= 2 and abs(ea - eb) <= 2 and mismatch <= 4
         assert rel < 1e-4
         assert np.median(err) < 1e-6 and np.quantile(err, 0.999) < 1e-4
+
+
+def test_ensemble_solves_match_oracle():
+    """Three grains of different grids, shapes and Debye lengths in one context:
+    each grain's standalone Newton solve (the others untouched) against the
+    oracle's."""
+    grains = [(64, 64, 0.2, -0.1, 1.0), (128, 64, -0.1, -0.2, 0.5), (32, 64, 0.05, -0.3, 2.0)]
+    sp = [apic.species(1.0, 100.0, 1.0, 1.0, 0.0, 0.0, 0)]
+    cfgs = [apic.grain_cfg(a, n1, n2, sp, x1_out=xo, kappa=k, phi_grain=-2.5, phi_out=0.0)
+            for n1, n2, a, xo, k in grains]
+    ctx = apic.apic_init(cfgs, apic.opts(precision=apic.APIC_FP64, inject=False, boltzmann_electrons=True))
+    try:
+        for gi, (n1, n2, a, xo, k) in enumerate(grains):
+            print(f"boltzmann ensemble grain {gi}", flush=True)
+            rho = 1.0 + 0.1 * smooth_density(n1, n2, seed=gi)
+            phi = apic.apic_solve_poisson(ctx, gi, rho, shape=(n2 + 1, n1 + 1)).reshape(n2 + 1, n1 + 1)
+            g = Grid(n1, n2, xo, a)
+            ref, _ = solve_boltzmann(g, assemble(g), rho, k, -2.5, 0.0)
+            err = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+            print(f"  rel err {err:.2e}")
+            assert err <= 1e-10
+    finally:
+        apic.apic_free(ctx)

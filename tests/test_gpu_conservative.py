@@ -81,3 +81,25 @@ def test_run_matches_oracle():
         print(f"s={s} particles {common} max {err.max():.2e} mismatch {mismatch}")
         assert mismatch == 0
         assert np.quantile(err, 0.999) < 1e-8
+
+
+def test_ensemble_solves_match_oracle():
+    """Three grains in one context with the conservative form: each grain's
+    standalone solve against the oracle's."""
+    grains = [(64, 64, 0.2, -0.1, 1.0), (128, 64, -0.1, -0.2, 0.5), (32, 64, 0.05, -0.3, 2.0)]
+    sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, 0)]
+    cfgs = [apic.grain_cfg(a, n1, n2, sp, x1_out=xo, kappa=k, phi_grain=-2.5, phi_out=0.0)
+            for n1, n2, a, xo, k in grains]
+    ctx = apic.apic_init(cfgs, apic.opts(precision=apic.APIC_FP64, inject=False, conservative_poisson=True))
+    try:
+        for gi, (n1, n2, a, xo, k) in enumerate(grains):
+            print(f"conservative ensemble grain {gi}", flush=True)
+            rho = smooth_density(n1, n2, seed=gi, amplitude=2.0)
+            phi = apic.apic_solve_poisson(ctx, gi, rho, shape=(n2 + 1, n1 + 1)).reshape(n2 + 1, n1 + 1)
+            g = Grid(n1, n2, xo, a)
+            ref = solve_fe(g, assemble_fe(g), rho * node_volumes(g), k, -2.5, 0.0)
+            err = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+            print(f"  rel err {err:.2e}")
+            assert err <= 1e-10
+    finally:
+        apic.apic_free(ctx)
