@@ -275,9 +275,10 @@ __device__ inline int xcd_line() {
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
 // On the finest level the axis rows j = 0 and j = n2 also couple to the rows
-// two away (one-sided d/dx2), which have their colour; they are relaxed as a
-// third colour after the other two, so that no line reads a line that is being
-// rewritten by the same launch.
+// two away (one-sided d/dx2), which have their colour: an axis row is relaxed
+// after both colours, by the workgroup of the odd row next to it, once that row
+// is solved (its other neighbours are even rows, already final), so that no line
+// reads a line that another workgroup of the same launch is rewriting.
 // With cl (the next coarser level) the sweep also applies the coarse-grid
 // correction u += P uc: a line's solution does not depend on its own old
 // value, only on its neighbour lines, so the first colour of the first sweep
@@ -292,13 +293,13 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     if (!level_active(D, ms)) return;
     const int n1 = D.n1, n2 = D.n2;
     int j;
+    int j_axis = -1;     // finest level (n2 >= 8), odd colour: the axis row solved after row j
     if constexpr (std::is_same<ST, FineStencil>::value) {
         const int line = xcd_line();
-        if (color == 2) {
-            if (line > 1) return;
-            j = line == 0 ? 0 : n2;
-        } else {
+        {
             j = color + 2 * line;
+            if (color == 1 && j == 1) j_axis = 0;
+            if (color == 1 && j == ((n2 & 1) ? n2 - 2 : n2 - 1)) j_axis = n2;
             if (j == 0 || j >= n2) {
                 // the axis rows are solved after the odd rows, which read
                 // them: a prolonging launch applies their correction here
@@ -332,7 +333,14 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     const ST st(D);
     const gptr<double> u = gbl(D.u);
     const gptr<const double> f = gbl(static_cast<const double*>(D.f));
-    const bool pro = cl != nullptr && cl[blockIdx.y].n1 != 0;
+    for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+        if (j_axis < 0) break;
+        // the axis row reads row j, just written by this workgroup
+        __syncthreads();
+        j = j_axis;
+    }
+    const bool pro = pass == 0 && cl != nullptr && cl[blockIdx.y].n1 != 0;
     if (pro) {
         const MGDesc& C = cl[blockIdx.y];
         const int ncx = C.n1 + 1;
@@ -374,6 +382,7 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     __syncthreads();
     pcr_solve<K, NT>(a, b, c, d, L, L);
     for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * rcp64(b[k]);
+    }
 }
 
 // Relaxation of LPB lines i1 = i (i = 1 + color, 3 + color, ...) per workgroup:
@@ -897,7 +906,7 @@ template <int K, int NT, class ST>
 static void relax_x1_launch(apic_ctx* ctx, int l, int color, bool prolong) {
     const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
     const size_t lds = x1_lds(mn1, prolong);
-    const int lines = color == 2 ? 2 : (mn2 + 1 - color + 1) / 2;
+    const int lines = (mn2 + 1 - color + 1) / 2;
     const int G = (int)ctx->grains.size();
     hipLaunchKernelGGL((k_relax_x1<K, NT, ST>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
                        ctx->mgdesc + (size_t)l * G, ctx->mgs, color,
@@ -936,12 +945,12 @@ static void relax_x2_k(apic_ctx* ctx, int l, int color) {
     }
 }
 
-// Both colours of the x1-line sweep of level l (on the finest level, then the
-// two axis rows); with prolong, the first colour also applies the coarse-grid
+// Both colours of the x1-line sweep of level l (on the finest level the odd
+// colour also solves the two axis rows); with prolong, the first colour also applies the coarse-grid
 // correction from level l + 1.
 template <class ST>
 static void sweep_x1(apic_ctx* ctx, int l, bool prolong) {
-    const int colors = std::is_same<ST, FineStencil>::value ? 3 : 2;
+    const int colors = 2;
     if (prolong && x1_lds(ctx->lvl_max_n1[l], true) > 65536) {
         // rows too long to stage two more of them: the correction separately
         const int G = (int)ctx->grains.size();
