@@ -637,10 +637,11 @@ int device_setup(apic_ctx* ctx, Grain& g, HostSetup& hs) {
             continue;
         }
         if (l == 0) TRY(alloc_t(ctx, &L.uprev, (size_t)L.nodes));   // the stored finest level
-        TRY(alloc_t(ctx, &L.st, (size_t)ST_COUNT * L.nodes));
-        stage.resize((size_t)ST_COUNT * L.nodes);
+        // node-major, ST_STRIDE doubles per node (the last one padding)
+        TRY(alloc_t(ctx, &L.st, (size_t)ST_STRIDE * L.nodes));
+        stage.assign((size_t)ST_STRIDE * L.nodes, 0.0);
         for (int k = 0; k < ST_COUNT; ++k)
-            std::copy(hs.levels[l].c[k].begin(), hs.levels[l].c[k].end(), stage.begin() + (size_t)k * L.nodes);
+            for (int o = 0; o < L.nodes; ++o) stage[(size_t)ST_STRIDE * o + k] = hs.levels[l].c[k][o];
         HIPCHK(ctx, hipMemcpy(L.st, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice));
     }
     if (!hs.inv.empty())

@@ -117,13 +117,17 @@ struct GrainDesc {
     DevCounters* ctr;
 };
 
+// Doubles per node of a stored stencil: the nine coefficients and one of
+// padding, so that a node's coefficients are five aligned 16-byte loads.
+constexpr int ST_STRIDE = 10;
+
 // One multigrid level of one grain.  n1 == 0: the grain has no such level.
 struct MGDesc {
     int n1, n2, nx, nodes;
     int coarsest;               // this is the grain's last level (dense solve)
     int m;                      // nodes of the dense system (coarsest only)
     double alpha, h1, h2;       // finest level: geometry of its stencil (evaluated at the nodes)
-    const double* st;           // coarse levels: 9 stencil arrays [k * nodes + node]
+    const double* st;           // stored levels: [node * ST_STRIDE + k], k = ST_C .. ST_NE
     double* u;
     double* f;
     double* uT;                 // finest level: u and f transposed (x2 fastest)

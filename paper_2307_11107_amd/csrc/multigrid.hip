@@ -168,29 +168,32 @@ struct Coef {
 // With Boltzmann electrons every level's diagonal carries the Newton term
 // (`shift`, subtracted from the centre coefficient).
 struct StoredStencil {
-    gptr<const double> st;
+    const double* st;
     const double* sh;
-    int nodes, n2;
-    __device__ explicit StoredStencil(const MGDesc& D) : st(gbl(D.st)), sh(D.shift), nodes(D.nodes), n2(D.n2) {}
+    int n2;
+    __device__ explicit StoredStencil(const MGDesc& D) : st(D.st), sh(D.shift), n2(D.n2) {}
     __device__ Coef at(int, int, size_t o) const {
-        const size_t n = (size_t)nodes;
+        // node-major: the nine coefficients of a node in five 16-byte loads
+        using d2 = double __attribute__((ext_vector_type(2)));
+        const gptr<const d2> p = gbl(reinterpret_cast<const d2*>(st + ST_STRIDE * o));
+        const d2 v0 = p[0], v1 = p[1], v2 = p[2], v3 = p[3], v4 = p[4];
         Coef c;
-        c.C = st[ST_C * n + o];
+        c.C = v0.x;
         if (sh) c.C -= gbl(sh)[o];
-        c.W = st[ST_W * n + o];
-        c.E = st[ST_E * n + o];
-        c.S = st[ST_S * n + o];
-        c.N = st[ST_N * n + o];
-        c.SW = st[ST_SW * n + o];
-        c.SE = st[ST_SE * n + o];
-        c.NW = st[ST_NW * n + o];
-        c.NE = st[ST_NE * n + o];
+        c.W = v0.y;
+        c.E = v1.x;
+        c.S = v1.y;
+        c.N = v2.x;
+        c.SW = v2.y;
+        c.SE = v3.x;
+        c.NW = v3.y;
+        c.NE = v4.x;
         c.nn = 0.0;
         c.ss = 0.0;
         return c;
     }
     __device__ double diag(int, int, size_t o) const {
-        return st[ST_C * (size_t)nodes + o] - (sh ? gbl(sh)[o] : 0.0);
+        return gbl(st)[ST_STRIDE * o + ST_C] - (sh ? gbl(sh)[o] : 0.0);
     }
 };
 
