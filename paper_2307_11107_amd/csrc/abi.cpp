@@ -780,6 +780,7 @@ int build_tables(apic_ctx* ctx) {
     ctx->lvl_max_n2.assign(NL, 0);
     ctx->lvl_max_nodes.assign(NL, 0);
     ctx->lvl_lines_x2.assign(NL, 0);
+    ctx->lvl_lines_x1.assign(NL, 0);
     ctx->lvl_max_m.assign(NL, 0);
     for (int l = 0; l < NL; ++l)
         for (int gi = 0; gi < G; ++gi) {
@@ -811,6 +812,7 @@ int build_tables(apic_ctx* ctx) {
                 ctx->lvl_max_n1[l] = std::max(ctx->lvl_max_n1[l], L.n1);
                 ctx->lvl_max_n2[l] = std::max(ctx->lvl_max_n2[l], L.n2);
                 ctx->lvl_lines_x2[l] += L.n1 / 2;
+                ctx->lvl_lines_x1[l] += L.n2 / 2;
             } else {
                 ctx->lvl_max_m[l] = std::max(ctx->lvl_max_m[l], d.m);
             }

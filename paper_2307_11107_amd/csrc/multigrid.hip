@@ -887,12 +887,17 @@ k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
 }
 
 // ------------------------------------------------------------------ launches
-// Line-solve launches.  A line gets 1024 threads beyond 512 unknowns, 512
-// beyond 256, else 256 (one equation per thread: a shorter PCR critical path,
-// and more waves per compute unit to cover the LDS round trips); the x2 sweeps
-// group LPB neighbouring lines of one colour per workgroup while
+// Line-solve launches.  An x1 line gets 1024 threads beyond 512 unknowns, else
+// 256, an x2 line 512 beyond 256, else 256 (fewer equations per thread, a
+// shorter PCR critical path).  Where a sweep has fewer than four lines per
+// compute unit, a line of 257 to 512 unknowns (x1) or more than 512 (x2) gets
+// one thread per unknown: with about one workgroup per compute unit the extra
+// waves cover the LDS round trips; with many lines they only add idle lanes.
+// The x2 sweeps group LPB neighbouring lines of one colour per workgroup while
 // that still leaves at least two workgroups per compute unit.
 static int round8(int x) { return (x + 7) / 8 * 8; }
+
+static bool few_lines(const apic_ctx* ctx, int lines) { return lines < 4 * ctx->num_cus; }
 
 static int pcr_k(int total, int nt) {
     const int k = (total + nt - 1) / nt;
@@ -966,7 +971,8 @@ static void sweep_x1(apic_ctx* ctx, int l, bool prolong) {
     for (int color = 0; color < colors; ++color) {
         const bool pro = prolong && color == 0;
         if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<1024, ST>(ctx, l, color, pro);
-        else if (ctx->lvl_max_n1[l] - 1 > 256) relax_x1_k<512, ST>(ctx, l, color, pro);
+        else if (ctx->lvl_max_n1[l] - 1 > 256 && few_lines(ctx, ctx->lvl_lines_x1[l]))
+            relax_x1_k<512, ST>(ctx, l, color, pro);
         else relax_x1_k<256, ST>(ctx, l, color, pro);
     }
 }
@@ -983,7 +989,7 @@ static void sweep_x2(apic_ctx* ctx, int l) {
     for (int color = 0; color < 2; ++color) {
         if (lpb == 4) relax_x2_k<4, 256, ST>(ctx, l, color);
         else if (lpb == 2) relax_x2_k<2, 256, ST>(ctx, l, color);
-        else if (Lx2 > 512) relax_x2_k<1, 1024, ST>(ctx, l, color);
+        else if (Lx2 > 512 && few_lines(ctx, lines)) relax_x2_k<1, 1024, ST>(ctx, l, color);
         else if (Lx2 > 256) relax_x2_k<1, 512, ST>(ctx, l, color);
         else relax_x2_k<1, 256, ST>(ctx, l, color);
     }
