@@ -299,28 +299,26 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     int j_axis = -1;     // finest level (n2 >= 8), odd colour: the axis row solved after row j
     if constexpr (std::is_same<ST, FineStencil>::value) {
         const int line = xcd_line();
-        {
-            j = color + 2 * line;
-            if (color == 1 && j == 1) j_axis = 0;
-            if (color == 1 && j == ((n2 & 1) ? n2 - 2 : n2 - 1)) j_axis = n2;
-            if (j == 0 || j >= n2) {
-                // the axis rows are solved after the odd rows, which read
-                // them: a prolonging launch applies their correction here
-                // (no line of this launch reads them)
-                if (color == 0 && line == 0 && cl != nullptr && cl[blockIdx.y].n1 != 0) {
-                    const MGDesc& C = cl[blockIdx.y];
-                    const int nx = n1 + 1, ncx = C.n1 + 1, n2c = C.n2;
-                    const gptr<double> u = gbl(D.u);
-                    const gptr<const double> uc = gbl(static_cast<const double*>(C.u));
-                    for (int t = threadIdx.x; t < 2 * nx; t += NT) {
-                        const int top = t >= nx, i = top ? t - nx : t;
-                        const int r = top ? n2 : 0, J = top ? n2c : 0;
-                        const int I0 = i >> 1, I1 = I0 + (i & 1);
-                        u[(size_t)r * nx + i] += 0.5 * (uc[(size_t)J * ncx + I0] + uc[(size_t)J * ncx + I1]);
-                    }
+        j = color + 2 * line;
+        if (color == 1 && j == 1) j_axis = 0;
+        if (color == 1 && j == ((n2 & 1) ? n2 - 2 : n2 - 1)) j_axis = n2;
+        if (j == 0 || j >= n2) {
+            // the axis rows are solved after the odd rows, which read them: a
+            // prolonging launch applies their correction here (no line of the
+            // even colour reads them)
+            if (color == 0 && line == 0 && cl != nullptr && cl[blockIdx.y].n1 != 0) {
+                const MGDesc& C = cl[blockIdx.y];
+                const int nx = n1 + 1, ncx = C.n1 + 1, n2c = C.n2;
+                const gptr<double> u = gbl(D.u);
+                const gptr<const double> uc = gbl(static_cast<const double*>(C.u));
+                for (int t = threadIdx.x; t < 2 * nx; t += NT) {
+                    const int top = t >= nx, i = top ? t - nx : t;
+                    const int r = top ? n2 : 0, J = top ? n2c : 0;
+                    const int I0 = i >> 1, I1 = I0 + (i & 1);
+                    u[(size_t)r * nx + i] += 0.5 * (uc[(size_t)J * ncx + I0] + uc[(size_t)J * ncx + I1]);
                 }
-                return;
             }
+            return;
         }
     } else {
         j = color + 2 * xcd_line();
