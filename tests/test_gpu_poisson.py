@@ -110,8 +110,10 @@ def test_in_step_solves_converge_in_few_cycles():
 def test_surface_field_matches_oracle(alpha):
     """The normal field on the grain (Section 2: it gives the surface charge
     and, through the Maxwell stress, the electric force) from the device's
-    potential against the oracle's formula on the oracle's potential."""
-    from oracle import field, geometry as geo
+    potential against the oracle's Simulation.surface_field on the oracle's
+    potential (that function is pinned to closed forms in
+    test_oracle_diagnostics.py)."""
+    from oracle.pic import Config, Simulation
     n1, n2 = 128, 96
     rho = smooth_density(n1, n2, seed=11, amplitude=2.0)
     ctx = _ctx(n1, n2, alpha, -0.1, 1.0)
@@ -121,11 +123,9 @@ def test_surface_field_matches_oracle(alpha):
     finally:
         apic.apic_free(ctx)
     g = Grid(n1, n2, -0.1, alpha)
-    phi = PoissonSolver(g).solve(source_from_density(rho, 1.0), -2.5, 0.0)
-    phi1, _ = field.nodal_gradient(phi, g)
-    x2 = g.x2_nodes()
-    x1R, x1Z, _, _ = geo.metric(np.full_like(x2, -1.0), x2, alpha)
-    ref = -np.hypot(x1R, x1Z) * phi1[:, 0]
+    sim = Simulation(Config(alpha=alpha, n1=n1, n2=n2, x1_out=-0.1, kappa=1.0), vacuum_field=False)
+    sim.set_phi(PoissonSolver(g).solve(source_from_density(rho, 1.0), -2.5, 0.0))
+    ref, _ = sim.surface_field()
     err = np.max(np.abs(en - ref)) / np.max(np.abs(ref))
     print(f"surface field alpha={alpha}: rel err {err:.2e}")
     assert err < 1e-9

@@ -103,7 +103,10 @@ def test_asymmetric_grain_force_and_torque_fp64():
     matched seeds over 100 steps."""
     w = scaled("c1", n_macro=30_000, n1=48, n2=48)
     w.update(alpha=0.2, wce=0.5)
-    ctx, sim = make_pair(w, apic.APIC_FP64, inject=True)
+    # in-step solves to 1e-13 so the field differs from the oracle's LU only by
+    # rounding; the force then follows the oracle's to rounding amplified by
+    # the particles' dynamics
+    ctx, sim = make_pair(w, apic.APIC_FP64, inject=True, poisson_tol=1e-13)
     try:
         for s in range(2):
             apic.apic_inject(ctx, 0, s)
@@ -116,7 +119,7 @@ def test_asymmetric_grain_force_and_torque_fp64():
         apic.apic_free(ctx)
     fe = abs(t["F_el_sum"] - sim.F_el_sum) / abs(sim.F_el_sum)
     print(f"electric force sum gpu {t['F_el_sum']:+.8e} oracle {sim.F_el_sum:+.8e} rel.err {fe:.2e}")
-    assert fe < 1e-3
+    assert fe < 1e-9
     for s in range(2):
         n_abs = max(int(sim.absorbed[s]), 1)
         allow = max(3, 0.01 * n_abs) / n_abs
