@@ -189,3 +189,100 @@ def test_escape_and_bookkeeping():
     sim.set_particles(0, x1, x2, [5.0, -3.0], [0.0, 0.0], [0.0, 0.0])
     sim.run(3)
     assert sim.escaped[0] == 1 and sim.absorbed[0] == 1 and sim.resident(0) == 0
+
+
+def _inside_brute(P, alpha):
+    """Inside the grain: r <= rho(x2), the grain radius of eq. (3) at x1 = -1."""
+    r = np.linalg.norm(P, axis=-1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        x2 = np.where(r > 0, P[..., 2] / np.where(r > 0, r, 1.0), 0.0)
+    return r <= geo.r_of(-1.0, x2, alpha)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.1, 0.2, -0.2, 0.24, -0.2499])
+def test_chord_impact_matches_dense_sampling(alpha):
+    """Any |alpha| < 1/4: the chord test's verdict and first crossing against a
+    brute-force scan of 8001 points per chord with the grain's definition
+    r <= rho(x2) (cases within 1e-7 of grazing, where the scan itself is unsure,
+    are left out)."""
+    rng = np.random.default_rng(7)
+    n = 2000
+    # start points just outside the grain, any direction and chord length
+    x2 = rng.uniform(-1, 1, n)
+    rg = geo.r_of(-1.0, x2, alpha)
+    r0 = rg * (1.0 + rng.uniform(1e-4, 0.6, n))
+    s = np.sqrt(1 - x2 * x2)
+    R, Z = r0 * s, r0 * x2
+    d = rng.normal(size=(n, 3))
+    d *= (rng.uniform(0.01, 2.5, n) / np.linalg.norm(d, axis=1))[:, None]
+    # half of the chords pass the origin at a distance r* between the smallest
+    # grain radius and r_c = 2/3 (there G is concave around the closest point),
+    # tangentially, near the end of the grain that is closest to the origin
+    m = n // 2
+    rmin = geo.r_of(-1.0, -np.sign(alpha) if alpha else 1.0, alpha)
+    rs = rng.uniform(rmin, max(rmin, 2.0 / 3.0) + 0.05, m)
+    th = rng.uniform(0.0, 0.5, m)
+    zs = -np.sign(alpha) if alpha else 1.0
+    Pc = np.stack([rs * np.sin(th), np.zeros(m), zs * rs * np.cos(th)], axis=1)
+    u = np.cross(Pc, rng.normal(size=(m, 3)))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    L = rng.uniform(0.05, 1.5, m)
+    f = rng.uniform(0.2, 0.8, m)
+    P0 = Pc - (f * L)[:, None] * u
+    R[:m] = np.hypot(P0[:, 0], P0[:, 1])
+    Z[:m] = P0[:, 2]
+    # rotate the chord so that its start is in the meridional plane Y = 0
+    c, s = P0[:, 0] / R[:m], P0[:, 1] / R[:m]
+    dd = L[:, None] * u
+    d[:m] = np.stack([c * dd[:, 0] + s * dd[:, 1], -s * dd[:, 0] + c * dd[:, 1], dd[:, 2]], axis=1)
+    keep = ~_inside_brute(np.stack([R, 0 * R, Z], axis=1), alpha)
+    R, Z, d = R[keep], Z[keep], d[keep]
+    hit, t = mover.chord_impact(R, Z, d[:, 0], d[:, 1], d[:, 2], alpha)
+    ts = np.linspace(0.0, 1.0, 8001)
+    P = np.stack([R[:, None] + ts * d[:, 0:1], ts * d[:, 1:2], Z[:, None] + ts * d[:, 2:3]], axis=-1)
+    ins = _inside_brute(P, alpha)
+    any_in = ins.any(axis=1)
+    # margin: distance of the chord's samples from the surface, relative
+    r = np.linalg.norm(P, axis=-1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        margin = np.min(np.abs(r - geo.r_of(-1.0, P[..., 2] / r, alpha)), axis=1)
+    sure = margin > 1e-7
+    assert np.array_equal(hit[sure], any_in[sure])
+    assert hit.sum() > 100 and (~hit).sum() > 100
+    # the first crossing lies within one sample of the scan's first inside point
+    k = np.argmax(ins, axis=1)
+    h = hit & any_in
+    assert np.all(t[h] <= ts[k[h]] + 1e-12)
+    assert np.all(t[h] >= ts[np.maximum(k[h] - 1, 0)] - 1e-12)
+    # and it is on the surface: r = rho(x2) there
+    Pi = np.stack([R + t * d[:, 0], t * d[:, 1], Z + t * d[:, 2]], axis=-1)[h]
+    ri = np.linalg.norm(Pi, axis=-1)
+    assert np.allclose(ri, geo.r_of(-1.0, Pi[:, 2] / ri, alpha), rtol=1e-12)
+
+
+def test_grazing_chord_on_a_dipole_grain_is_absorbed():
+    """alpha = 0.2: a chord whose end points and whose closest approach to the
+    origin are all outside the grain, but which clips it between them, is an
+    absorption (the earlier closest-approach test missed it)."""
+    alpha = 0.2
+    R = np.array([1.01])
+    Z = np.array([-0.1])
+    d = np.array([0.0, 0.0, 0.45])
+    for t in (0.0, 1.0):
+        x1, _ = geo.conforming_of(R + t * d[0], Z + t * d[2], alpha)
+        assert x1[0] > -1.0
+    tc = -(Z[0] * d[2]) / (d[2] ** 2)
+    x1c, _ = geo.conforming_of(R, Z + tc * d[2], alpha)
+    assert x1c[0] > -1.0
+    hit, t = mover.chord_impact(R, Z, d[0:1], d[1:2], d[2:3], alpha)
+    assert hit[0]
+    x1i, _ = geo.conforming_of(R, Z + t * d[2], alpha)
+    assert abs(x1i[0] + 1.0) < 1e-12
+    # a chord that passes the origin deep inside the grain (where x1 from eq. 2
+    # is not below -1 any more) is absorbed at its first crossing
+    P0, d = np.array([1.2, 0.0, -0.6]), np.array([-2.4, 0.0, 1.2])
+    hit, t = mover.chord_impact(P0[0:1], P0[2:3], d[0:1], d[1:2], d[2:3], alpha)
+    assert hit[0] and 0.1 < t[0] < 0.25
+    Pi = P0 + t[0] * d
+    x1i, _ = geo.conforming_of(np.hypot(Pi[0], Pi[1]), Pi[2], alpha)
+    assert abs(x1i + 1.0) < 1e-12
