@@ -124,6 +124,9 @@ typedef struct {
     double weight[APIC_MAX_SPECIES];        /* macro-particle weights in use          */
     double F_el_sum;                        /* sum over steps of the electric force
                                                F_Z on the grain, units eps0 Te^2/e^2  */
+    uint64_t unconverged_solves;            /* in-step field solves that stopped at
+                                               apic_opts.poisson_max_cycles before
+                                               reaching poisson_tol (0 in a healthy run) */
     uint64_t* count;                        /* absorbed particles per bin             */
     double* charge;                         /* sum q w                                */
     double* pR;                             /* sum m w v_R  (impact meridional frame) */
@@ -177,8 +180,10 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
  * n < 0 with all arrays NULL: loads cfg.sp[species].n_macro particles uniform in
  * physical volume (eq. 5) with Maxwellian velocities, drawn on the device from
  * Philox4x32-10 (Salmon et al., SC'11) with the grain's key.
- * Particles outside the domain are rejected with APIC_EINVAL; more than the
- * capacity gives APIC_ENOMEM.  The field is recomputed before the next step. */
+ * Particles outside the domain (-1 < x1 < x1_out, |x2| <= 1) or with a
+ * non-finite velocity are rejected with APIC_EINVAL before any device work
+ * (nothing is changed); more than the capacity gives APIC_ENOMEM.  The field is
+ * recomputed before the next step. */
 int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n,
                 const double* x1, const double* x2,
                 const double* vR, const double* vZ, const double* vTheta);
@@ -207,7 +212,8 @@ int apic_tallies(apic_ctx* ctx, int32_t grain, apic_tally* out);
 /* Copies the live particles of one species to the host, sorted by id.
  * cap is the length of the arrays; *n_out receives the number of particles
  * (APIC_EINVAL if it exceeds cap).  Positions are returned as (x1, x2) in FP64.
- * id may be NULL. */
+ * id may be NULL.  APIC_ESTATE if the species was never populated (no
+ * apic_inject for it and no step with injection). */
 int apic_particles(apic_ctx* ctx, int32_t grain, int32_t species, int64_t cap,
                    double* x1, double* x2, double* vR, double* vZ, double* vTheta,
                    int64_t* id, int64_t* n_out);
@@ -225,7 +231,8 @@ int apic_fields(apic_ctx* ctx, int32_t grain, double* phi, double* rho);
 int apic_surface_field(apic_ctx* ctx, int32_t grain, double* E_n);
 
 /* Enables (1) or disables (0) HIP-event timing of the kernels, resetting the
- * accumulated times; apic_timing synchronises and returns them. */
+ * accumulated times; apic_timing synchronises and returns them (APIC_ESTATE if
+ * timing was never enabled on the context). */
 int apic_set_profiling(apic_ctx* ctx, int32_t on);
 int apic_timing(apic_ctx* ctx, apic_kernel_times* out);
 

@@ -103,6 +103,8 @@ def chord_impact(R, Z, dX, dY, dZ, alpha):
     found by bisection on G.  Only the part of the chord inside r <= rho_max
     (the largest grain radius) can meet the grain."""
     R, Z, dX, dY, dZ = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (R, Z, dX, dY, dZ)))
+    shape = R.shape
+    R, Z, dX, dY, dZ = (v.ravel() for v in (R, Z, dX, dY, dZ))
     rho_max = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * abs(alpha)))
     a = dX * dX + dY * dY + dZ * dZ
     b = R * dX + Z * dZ
@@ -110,20 +112,27 @@ def chord_impact(R, Z, dX, dY, dZ, alpha):
     moving = a > 0.0
     aa = np.where(moving, a, 1.0)
     disc = b * b - aa * (c - rho_max * rho_max)
-    cand = moving & (disc >= 0.0)
     sq = np.sqrt(np.maximum(disc, 0.0))
     lo = np.maximum(0.0, (-b - sq) / aa)
     hi = np.minimum(1.0, (-b + sq) / aa)
-    cand &= lo <= hi
+    # the chords that enter r <= rho_max; the others miss the grain
+    cand = moving & (disc >= 0.0) & (lo <= hi)
+    hit_all = np.zeros(R.shape, dtype=bool)
+    t_all = np.zeros(R.shape)
+    k = np.nonzero(cand)[0]
+    if k.size == 0:
+        return hit_all.reshape(shape), t_all.reshape(shape)
+    aa, b, c, Z, dZ, lo, hi = aa[k], b[k], c[k], Z[k], dZ[k], lo[k], hi[k]
+    cand = np.ones(k.size, dtype=bool)
     ts = -b / aa
     rs2 = np.maximum(c - b * b / aa, 0.0)
     rc = (1.0 + np.sqrt(1.0 + 18.0 * rs2)) / 6.0
     sc = np.where(rs2 < 4.0 / 9.0, np.sqrt(np.maximum(rc * rc - rs2, 0.0) / aa), 0.0)
     G = lambda t: _chord_G(aa, b, c, Z, dZ, t, alpha)[0]
     dG = lambda t: _chord_G(aa, b, c, Z, dZ, t, alpha)[1]
-    found = np.zeros(R.shape, dtype=bool)
-    t_out = np.zeros(R.shape)
-    t_in = np.zeros(R.shape)
+    found = np.zeros(k.size, dtype=bool)
+    t_out = np.zeros(k.size)
+    t_in = np.zeros(k.size)
     pieces = ((lo, np.minimum(hi, ts - sc), True),
               (np.maximum(lo, ts - sc), np.minimum(hi, ts + sc), False),
               (np.maximum(lo, ts + sc), hi, True))
@@ -154,7 +163,9 @@ def chord_impact(R, Z, dX, dY, dZ, alpha):
         v = np.where(inside, m, v)
         u = np.where(inside, u, m)
     t_hit = np.where(G(t_out) <= 0.0, t_out, v)
-    return found, np.where(found, t_hit, 0.0)
+    hit_all[k] = found
+    t_all[k] = np.where(found, t_hit, 0.0)
+    return hit_all.reshape(shape), t_all.reshape(shape)
 
 
 def grain_hits(R, Z, vR, vZ, vT, step, x1_new, alpha):

@@ -127,6 +127,7 @@ def apic_tallies(ctx, grain, n_species, n_bins):
     out["weight"] = np.array([t.weight[s] for s in range(ns)])
     out["steps"] = int(t.steps)
     out["F_el_sum"] = float(t.F_el_sum)
+    out["unconverged_solves"] = int(t.unconverged_solves)
     return out
 
 

@@ -37,6 +37,7 @@ class apic_tally(C.Structure):
                 ("escaped", C.c_uint64 * APIC_MAX_SPECIES), ("resident", C.c_uint64 * APIC_MAX_SPECIES),
                 ("particle_steps", C.c_uint64 * APIC_MAX_SPECIES),
                 ("weight", C.c_double * APIC_MAX_SPECIES), ("F_el_sum", C.c_double),
+                ("unconverged_solves", C.c_uint64),
                 ("count", C.POINTER(C.c_uint64)), ("charge", C.POINTER(C.c_double)),
                 ("pR", C.POINTER(C.c_double)), ("pZ", C.POINTER(C.c_double)),
                 ("L", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double))]

@@ -179,6 +179,14 @@ int solve_linear(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int o
             TRY(read_batch(ctx, b));
         }
         ctx->pred_cycles = b.max_cycles;
+        if (b.pending > 0) {
+            // stopped at the cycle cap: counted per grain, reported in the tallies
+            const int G = (int)ctx->grains.size();
+            std::vector<MGState> m(G);
+            HIPCHK(ctx, hipMemcpy(m.data(), ctx->mgs, sizeof(MGState) * G, hipMemcpyDeviceToHost));
+            for (int g = 0; g < G; ++g)
+                if (!m[g].done) ++ctx->grains[g].unconverged;
+        }
     } else {
         HIPCHK(ctx, launch_set_boundary(ctx));
         HIPCHK(ctx, mg_begin(ctx, tol, only, false));
@@ -1182,6 +1190,14 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
     const int64_t count = load ? g.cfg.sp[species].n_macro : n;
     if (count > g.capacity[species])
         return fail(ctx, APIC_ENOMEM, "particle count exceeds the species capacity");
+    // host arrays are checked before any device work
+    for (int64_t k = 0; !load && k < count; ++k) {
+        if (!(x1[k] > -1.0 && x1[k] < g.cfg.x1_out && x2[k] >= -1.0 && x2[k] <= 1.0))
+            return fail(ctx, APIC_EINVAL, "particle " + std::to_string(k) +
+                                              " outside the domain (-1 < x1 < x1_out, |x2| <= 1)");
+        if (!(std::isfinite(vR[k]) && std::isfinite(vZ[k]) && std::isfinite(vTheta[k])))
+            return fail(ctx, APIC_EINVAL, "particle " + std::to_string(k) + " has a non-finite velocity");
+    }
     const int s = species;
     g.cur[s] = 0;
     if (load) {
@@ -1231,6 +1247,7 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
     TRY(sort_one(ctx, grain, s));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     g.field_stale = true;
+    g.loaded[s] = true;
     return APIC_OK;
 }
 
@@ -1238,6 +1255,9 @@ int apic_step(apic_ctx* ctx, int64_t n_steps) {
     if (!ctx) return fail(nullptr, APIC_EINVAL, "null context");
     if (n_steps < 0) return fail(ctx, APIC_EINVAL, "n_steps < 0");
     int64_t left = n_steps;
+    if (ctx->opts.inject && n_steps > 0)
+        for (auto& g : ctx->grains)
+            for (int s = 0; s < g.ns; ++s) g.loaded[s] = true;
     if (ctx->opts.autotune && !ctx->tuned && left > 0) TRY(autotune(ctx, &left));
     for (int64_t k = 0; k < left; ++k) TRY(do_step(ctx));
     if (n_steps > 0) TRY(check_overflow(ctx));
@@ -1293,6 +1313,7 @@ int apic_tallies(apic_ctx* ctx, int32_t grain, apic_tally* out) {
         out->weight[s] = on ? g.sp[s].w : 0.0;
     }
     out->F_el_sum = h.F_el_sum;
+    out->unconverged_solves = g.unconverged;
     const size_t nb = (size_t)g.ns * g.gp.n_bins;
     double* dst[5] = {out->charge, out->pR, out->pZ, out->L, out->energy};
     for (int k = 0; k < 5; ++k)
@@ -1314,6 +1335,9 @@ int apic_particles(apic_ctx* ctx, int32_t grain, int32_t species, int64_t cap, d
     if (species < 0 || species >= g.ns) return fail(ctx, APIC_EINVAL, "species index out of range");
     if (!n_out || cap < 0 || (cap > 0 && !(x1 && x2 && vR && vZ && vTheta)))
         return fail(ctx, APIC_EINVAL, "bad output arrays");
+    if (!g.loaded[species])
+        return fail(ctx, APIC_ESTATE, "species " + std::to_string(species) +
+                                          " holds no particles: load them with apic_inject (or step with injection) first");
     DevCounters h;
     HIPCHK(ctx, hipMemcpyAsync(&h, g.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1423,11 +1447,14 @@ int apic_set_profiling(apic_ctx* ctx, int32_t on) {
     }
     ctx->timed_particle_steps = -pushed;
     ctx->profiling = on != 0;
+    ctx->profiled |= ctx->profiling;
     return APIC_OK;
 }
 
 int apic_timing(apic_ctx* ctx, apic_kernel_times* out) {
     if (!ctx || !out) return fail(ctx, APIC_EINVAL, "null argument");
+    if (!ctx->profiling && !ctx->profiled)
+        return fail(ctx, APIC_ESTATE, "timing was never enabled: call apic_set_profiling(ctx, 1) first");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     for (auto& t : ctx->timers) {
         float ms = 0;

@@ -180,6 +180,8 @@ struct Grain {
     std::vector<double> vol_host;
     uint64_t inj_inc[APIC_MAX_SPECIES] = {0, 0};    // injection per step, 2^-32 units
     uint64_t step_index = 0;
+    uint64_t unconverged = 0;       // in-step solves stopped at the cycle cap
+    bool loaded[APIC_MAX_SPECIES] = {false, false};  // particles set, loaded or injected
     bool field_stale = true;
     int64_t capacity[APIC_MAX_SPECIES] = {0, 0};
     PBuf buf[APIC_MAX_SPECIES][2];
@@ -271,6 +273,7 @@ struct apic_ctx {
     hipGraphExec_t graph[apic::G_COUNT] = {};
     // profiling
     bool profiling = false;
+    bool profiled = false;                  // timing was enabled at some point
     std::vector<apic::TimerPair> timers;   // recorded, not yet harvested
     std::vector<hipEvent_t> event_pool;
     double t_ms[4] = {0, 0, 0, 0};

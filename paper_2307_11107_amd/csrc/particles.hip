@@ -58,32 +58,116 @@ __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
     __syncthreads();
 }
 
-// ----------------------------------------------------------------- impact tally
-// Bisection on x1 + 1 along the chord P(t) = (R + t dX, t dY, Z + t dZ) between
-// t = 0 (outside) and t_in (inside); tallies at the impact point with the
-// velocity rotated into the impact point's meridional plane.
-// The impact parameters come as scalars (no struct by reference), so a caller's
-// parameter structs can stay in registers.
+// ----------------------------------------------------------------- grain impact
+// The chord of a step, P(t) = (R + t dX, t dY, Z + t dZ) for t in [0, 1], meets
+// the grain where eq. (2)'s x1 <= -1, multiplied by r^3, holds:
+// G = r^3 - r^2 - alpha Z <= 0.  That is the shell between the two roots of
+// r^2 - r - alpha x2, whose outer root is the grain radius of eq. (3); the core
+// next to the origin (where x1 of eq. 2 is not below -1) is reached only
+// through the shell, so the chord's first point with G <= 0 is its first point
+// on the grain.  With r^2 = c + 2 b t + a t^2 (a = |d|^2, b = P0.d,
+// c = |P0|^2) and r* the chord's closest distance to the origin,
+// d2G/dt2 = a (6 r^2 - 2 r - 3 r*^2) / r: G is concave where
+// r < r_c = (1 + sqrt(1 + 18 r*^2)) / 6 (only if r* < 2/3) and convex elsewhere,
+// so the chord falls into at most three pieces -- convex, concave, convex.
+template <typename T>
+struct Chord {
+    T a, b, c, Z, dZ, alpha;
+    __device__ T G(T t) const {
+        const T q = c + t * (T(2) * b + a * t);
+        const T r = sqrt(q > T(0) ? q : T(0));
+        return r * q - q - alpha * (Z + t * dZ);
+    }
+    __device__ T dG(T t) const {
+        const T q = c + t * (T(2) * b + a * t);
+        const T r = sqrt(q > T(0) ? q : T(0));
+        return (T(3) * r - T(2)) * (b + a * t) - alpha * dZ;
+    }
+};
+
+// t of the chord's first point inside the grain, or -1 if the chord misses it.
+// Only the part within r <= rho_max (the largest grain radius) is searched.
+// The pieces are taken in order: a convex piece's minimum is the root of dG/dt
+// (bisection), a concave piece's lies at an end; in the first piece whose
+// minimum is <= 0 the crossing is unique (G falls monotonically to a convex
+// minimum; a concave piece positive at its start changes sign once) and is
+// found by bisection on G.
+template <typename T>
+__device__ __attribute__((noinline)) T chord_hit(T rho_max, T alpha, T R, T Z, T dX, T dY, T dZ, int iters) {
+    const Chord<T> ch{dX * dX + dY * dY + dZ * dZ, R * dX + Z * dZ, R * R + Z * Z, Z, dZ, alpha};
+    if (!(ch.a > T(0))) return T(-1);
+    const T disc = ch.b * ch.b - ch.a * (ch.c - rho_max * rho_max);
+    if (!(disc >= T(0))) return T(-1);
+    const T sq = sqrt(disc);
+    const T lo = max(T(0), (-ch.b - sq) / ch.a), hi = min(T(1), (-ch.b + sq) / ch.a);
+    if (!(lo <= hi)) return T(-1);
+    const T ts = -ch.b / ch.a;
+    const T rs2 = max(T(0), ch.c - ch.b * ch.b / ch.a);
+    T sc = T(0);
+    if (rs2 < T(4) / T(9)) {
+        const T rc = (T(1) + sqrt(T(1) + T(18) * rs2)) / T(6);
+        sc = sqrt(max(T(0), rc * rc - rs2) / ch.a);
+    }
+    for (int k = 0; k < 3; ++k) {
+        const T L = k == 0 ? lo : max(lo, k == 1 ? ts - sc : ts + sc);
+        const T U = k == 2 ? hi : min(hi, k == 0 ? ts - sc : ts + sc);
+        if (!(L <= U)) continue;
+        T tm;
+        if (k == 1) {
+            tm = ch.G(L) <= ch.G(U) ? L : U;
+        } else if (ch.dG(L) >= T(0)) {
+            tm = L;
+        } else if (ch.dG(U) <= T(0)) {
+            tm = U;
+        } else {
+            T u = L, v = U;
+            for (int it = 0; it < iters; ++it) {
+                const T m = T(0.5) * (u + v);
+                const bool up = ch.dG(m) >= T(0);
+                v = up ? m : v;
+                u = up ? u : m;
+            }
+            tm = v;
+        }
+        if (!(ch.G(tm) <= T(0))) continue;
+        if (ch.G(L) <= T(0)) return L;
+        T u = L, v = tm;
+        for (int it = 0; it < iters; ++it) {
+            const T m = T(0.5) * (u + v);
+            const bool in = ch.G(m) <= T(0);
+            v = in ? m : v;
+            u = in ? u : m;
+        }
+        return v;
+    }
+    return T(-1);
+}
+
+// Chord test of a step: -1 unless the chord comes within rho_max of the
+// origin (the usual case, decided here without the search).
+template <typename T>
+__device__ inline T grain_chord(T rho_max, T alpha, T R, T Z, T dX, T dY, T dZ, int iters) {
+    const T dd = dX * dX + dY * dY + dZ * dZ;
+    const T pd = -(R * dX + Z * dZ);
+    const T tc = pd > T(0) ? (pd < dd ? pd / dd : T(1)) : T(0);
+    const T Xc = R + tc * dX, Yc = tc * dY, Zc = Z + tc * dZ;
+    if (Xc * Xc + Yc * Yc + Zc * Zc > rho_max * rho_max) return T(-1);
+    return chord_hit<T>(rho_max, alpha, R, Z, dX, dY, dZ, iters);
+}
+
+// Tallies of an absorbed particle at the chord's impact point t: the velocity
+// is rotated into the impact point's meridional plane.  The impact parameters
+// come as scalars (no struct by reference), so a caller's parameter structs can
+// stay in registers.
 struct ImpactSpecies {
     double q, m, w, e_bind;
 };
 
 template <typename T>
-__device__ __attribute__((noinline)) void tally_impact(double alpha_d, int n_bins, ImpactSpecies sp, int s, int ns,
-                             T R, T Z, T dX, T dY, T dZ, T t_in, T vR, T vZ, T vT,
-                             double* tally, unsigned long long* tally_count, int iters) {
-    const T alpha = (T)alpha_d;
-    T lo = 0, hi = t_in;
-    for (int it = 0; it < iters; ++it) {
-        const T mid = T(0.5) * (lo + hi);
-        const T X = R + mid * dX, Y = mid * dY, Zc = Z + mid * dZ;
-        const T r = sqrt(X * X + Y * Y + Zc * Zc);
-        const T x1 = x1_of(r, Zc / r, alpha);
-        const bool inside = !(x1 > T(-1));
-        hi = inside ? mid : hi;
-        lo = inside ? lo : mid;
-    }
-    const T X = R + hi * dX, Y = hi * dY, Zi = Z + hi * dZ;
+__device__ __attribute__((noinline)) void tally_impact(int n_bins, ImpactSpecies sp, int s, int ns,
+                             T R, T Z, T dX, T dY, T dZ, T t, T vR, T vZ, T vT,
+                             double* tally, unsigned long long* tally_count) {
+    const T X = R + t * dX, Y = t * dY, Zi = Z + t * dZ;
     const T Ri = sqrt(X * X + Y * Y);
     const T ri = sqrt(Ri * Ri + Zi * Zi);
     const T x2 = Zi / ri;
@@ -102,25 +186,6 @@ __device__ __attribute__((noinline)) void tally_impact(double alpha_d, int n_bin
     atomic_add_f64(&tally[3 * stride + o], sp.m * sp.w * (double)Ri * vTi);
     atomic_add_f64(&tally[4 * stride + o], sp.w * (0.5 * sp.m * v2 + sp.e_bind));
     gadd(&tally_count[o], 1ull);
-}
-
-// Closest approach of the chord to the origin; returns t in (0,1) if the point
-// there is inside the grain, else -1.
-template <typename T>
-__device__ inline T chord_inside(const GrainParams& gp, T R, T Z, T dX, T dY, T dZ) {
-    const T dd = dX * dX + dY * dY + dZ * dZ;
-    const T pd = -(R * dX + Z * dZ);
-    // the closest approach lies strictly inside the step only if 0 < pd < dd
-    if (!(pd > T(0) && pd < dd)) return T(-1);
-    const T tc = pd / dd;
-    if (!(tc > T(0) && tc < T(1))) return T(-1);
-    const T X = R + tc * dX, Y = tc * dY, Zc = Z + tc * dZ;
-    const T rc2 = X * X + Y * Y + Zc * Zc;
-    const T rg = (T)gp.r_grain_max;
-    if (rc2 > rg * rg) return T(-1);
-    const T rc = sqrt(rc2);
-    const T x1 = x1_of(rc, Zc / rc, (T)gp.alpha);
-    return (x1 > T(-1)) ? T(-1) : tc;
 }
 
 // ----------------------------------------------------------------- FP32 split push
@@ -306,12 +371,12 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
         if (i2n > n2 - 1) { i2n = n2 - 1; f2n = 0.99999994f; }
     }
 
-    // boundaries
-    const float tmid = chord_inside<float>(gp, R, Z, dX, dY, dZ);
-    if (i1n < 0 || tmid > 0.f) {
-        const float t_in = tmid > 0.f ? tmid : 1.f;
-        tally_impact<float>(gp.alpha, gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
-                            dY, dZ, t_in, vR, vZ, vT, tally, tally_count, 24);
+    // boundaries: absorbed if the chord meets the grain (or, by rounding next
+    // to the surface, only the end point lies inside: tallied there)
+    const float t_hit = grain_chord<float>((float)gp.r_grain_max, alpha, R, Z, dX, dY, dZ, 24);
+    if (i1n < 0 || t_hit >= 0.f) {
+        tally_impact<float>(gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
+                            dY, dZ, t_hit >= 0.f ? t_hit : 1.f, vR, vZ, vT, tally, tally_count);
         *cell = DEAD;
         return 1;
     }
@@ -369,11 +434,10 @@ __device__ inline int drift_and_bound64(const GrainParams& gp, const SpeciesPara
     const double rn = sqrt(Rn * Rn + Zn * Zn);
     x2n = Zn / rn;
     x1n = x1_of(rn, x2n, gp.alpha);
-    const double tmid = chord_inside<double>(gp, R, Z, dX, dY, dZ);
-    if (!(x1n > -1.0) || tmid > 0.0) {
-        tally_impact<double>(gp.alpha, gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
-                             dY, dZ, tmid > 0.0 ? tmid : 1.0, vR, vZ,
-                             vT, tally, tally_count, 48);
+    const double t_hit = grain_chord<double>(gp.r_grain_max, gp.alpha, R, Z, dX, dY, dZ, 60);
+    if (!(x1n > -1.0) || t_hit >= 0.0) {
+        tally_impact<double>(gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
+                             dY, dZ, t_hit >= 0.0 ? t_hit : 1.0, vR, vZ, vT, tally, tally_count);
         return 1;
     }
     if (x1n >= gp.x1_out) return 2;

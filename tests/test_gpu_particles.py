@@ -90,8 +90,8 @@ def test_fp64_frozen_field_push_matches_oracle(alpha, wce):
                 err, common = particle_error(dev, ora, sim.grid, vs)
                 mismatch = len(dev["id"]) + len(ora["id"]) - 2 * common
                 print(f"fp64 s={s} steps={steps} max {err.max():.2e} live {len(ora['id'])} mismatch {mismatch}")
-                assert mismatch <= max(1, len(ora["id"]) // 1000)
-                assert np.quantile(err, 0.999) < tol
+                assert mismatch == 0
+                assert err.max() < tol
         t = apic.apic_tallies(ctx, 0, 2, w["n2"])
         for s in range(2):
             assert abs(int(t["absorbed"][s]) - int(sim.absorbed[s])) <= 2
@@ -191,5 +191,100 @@ def test_edge_cases(precision):
         assert e.value.code == apic.APIC_ENOMEM
         with pytest.raises(apic.ApicError):
             apic.apic_particles(ctx, 0, 5, 10)
+    finally:
+        apic.apic_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_grazing_chords_match_oracle(precision):
+    """alpha = 0.2 with lambda_D/R0 = 5 (a thermal electron moves ~0.25 R0 per
+    step): particles just outside the grain with fast tangential velocities,
+    many of whose chords clip the grain between an outside start, an outside
+    end and an outside closest approach to the origin.  One frozen-field step in
+    the vacuum field: absorbed and escaped counts, the impact tallies bin by bin
+    and the survivors against the oracle."""
+    from oracle import geometry as geo
+    w = scaled("c1", n1=64, n2=64)
+    w.update(alpha=0.2, kappa=5.0, mi=25.0)
+    ctx, sim = make_pair(w, precision, inject=False, frozen=True, n_macro=0, weight=0.01)
+    rng = np.random.default_rng(5)
+    n = 20000
+    clipped_only = 0
+    try:
+        for s, vs in ((0, 1.0), (1, 0.3)):
+            x1 = -1.0 + rng.uniform(1e-4, 0.05, n)
+            x2 = rng.uniform(-1.0, 1.0, n)
+            R, Z = geo.cyl_of(x1, x2, w["alpha"])
+            x1R, x1Z, _, _ = geo.metric(x1, x2, w["alpha"])
+            gn = np.hypot(x1R, x1Z)
+            tR, tZ = x1Z / gn, -x1R / gn                 # tangent of the x1 surface
+            vt = rng.normal(0.0, 3.0 * vs, n)
+            vn = rng.normal(0.0, 0.3 * vs, n)
+            vR = vt * tR + vn * x1R / gn
+            vZ = vt * tZ + vn * x1Z / gn
+            vT = rng.normal(0.0, vs, n)
+            apic.apic_inject(ctx, 0, s, x1, x2, vR, vZ, vT)
+            sim.set_particles(s, x1, x2, vR, vZ, vT)
+            # chords that the end point and closest-approach tests alone miss
+            st = w["kappa"] * w["dt"]
+            d = np.stack([st * vR, st * vT, st * vZ], axis=1)
+            Xe, Ye, Ze = R + d[:, 0], d[:, 1], Z + d[:, 2]
+            x1e, _ = geo.conforming_of(np.hypot(Xe, Ye), Ze, w["alpha"])
+            tc = np.clip(-(R * d[:, 0] + Z * d[:, 2]) / np.einsum("ij,ij->i", d, d), 0, 1)
+            x1c, _ = geo.conforming_of(np.hypot(R + tc * d[:, 0], tc * d[:, 1]), Z + tc * d[:, 2], w["alpha"])
+            from oracle import mover
+            hit, _ = mover.chord_impact(R, Z, d[:, 0], d[:, 1], d[:, 2], w["alpha"])
+            clipped_only += int(np.sum(hit & (x1e > -1) & (x1c > -1)))
+        apic.apic_step(ctx, 1)
+        sim.run(1)
+        t = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        print(f"precision={precision}: {clipped_only} chords clip the grain between outside points", flush=True)
+        assert clipped_only > 50
+        for s, vs in ((0, 1.0), (1, 0.3)):
+            na, nb = int(t["absorbed"][s]), int(sim.absorbed[s])
+            ca, cb = t["count"][s], sim.tally["count"][s]
+            print(f"s={s} absorbed gpu {na} oracle {nb}; per-bin count differences {int(np.abs(ca - cb).sum())}")
+            if precision == FP64:
+                assert na == nb and np.array_equal(ca, cb)
+            else:
+                # a chord grazing the surface within FP32 rounding may go either way
+                assert abs(na - nb) <= 2 and np.abs(ca - cb).sum() <= 4
+            for k in ("charge", "pR", "pZ", "L", "energy"):
+                a, b = t[k][s], sim.tally[k][s]
+                err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+                print(f"  {k:6s} per-bin max err (of the largest bin) {err:.2e}")
+                assert err < (1e-10 if precision == FP64 else 2e-2)
+            dev = apic.apic_particles(ctx, 0, s, n)
+            ora = sim.particles(s)
+            err, common = particle_error(dev, ora, sim.grid, vs)
+            assert common >= len(ora["id"]) - 2
+            assert np.quantile(err, 0.999) < (1e-11 if precision == FP64 else 1e-5)
+    finally:
+        apic.apic_free(ctx)
+
+
+def test_call_order_and_invalid_particles_rejected():
+    """APIC_ESTATE for read-back of a species that was never populated and for
+    timing that was never enabled; APIC_EINVAL for a non-finite velocity, with
+    the species left as it was."""
+    w = scaled("c1", n1=16, n2=16)
+    ctx, _ = make_pair(w, FP32, inject=False, capacity=5000)
+    try:
+        with pytest.raises(apic.ApicError) as e:
+            apic.apic_particles(ctx, 0, 1, 10)
+        assert e.value.code == apic.APIC_ESTATE
+        with pytest.raises(apic.ApicError) as e:
+            apic.apic_timing(ctx)
+        assert e.value.code == apic.APIC_ESTATE
+        apic.apic_inject(ctx, 0, 0, [-0.5, -0.4], [0.1, 0.2], [0.0, 0.1], [0.0, 0.0], [0.0, 0.0])
+        for bad in (np.nan, np.inf, -np.inf):
+            with pytest.raises(apic.ApicError) as e:
+                apic.apic_inject(ctx, 0, 0, [-0.5, -0.3], [0.1, 0.0], [0.0, 0.0], [bad, 0.0], [0.0, 0.0])
+            assert e.value.code == apic.APIC_EINVAL
+        p = apic.apic_particles(ctx, 0, 0, 10)
+        assert len(p["id"]) == 2 and np.allclose(p["x2"], [0.1, 0.2], atol=1e-6)
+        apic.apic_set_profiling(ctx, True)
+        apic.apic_step(ctx, 1)
+        assert apic.apic_timing(ctx)["steps"] == 1
     finally:
         apic.apic_free(ctx)
