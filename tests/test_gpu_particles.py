@@ -109,8 +109,9 @@ def test_fp32_split_frozen_field_push_matches_oracle(alpha, wce):
     2^-24 relative perturbation of the initial state already moves the FP64
     oracle's own trajectories by ~1e-6 (median) and up to ~1e-4 after 100 steps.
     The bar is therefore: median error below 1e-5 for both species, ions
-    (well-conditioned) below 1e-5 at the 99.9th percentile, and the 99th
-    percentile within 10x of that one-rounding sensitivity of the FP64 dynamics."""
+    (well-conditioned) below 1e-5 at the 99.9th percentile, the 99th
+    percentile within 10x of that one-rounding sensitivity of the FP64 dynamics,
+    and particles absorbed or escaped in one run only at most 1e-4 of them."""
     w = scaled("c1", n1=64, n2=48)
     w.update(alpha=alpha, wce=wce, mi=25.0)
     ctx, sim = _frozen_pair(w, FP32, 0, seed=8)
@@ -136,7 +137,8 @@ def test_fp32_split_frozen_field_push_matches_oracle(alpha, wce):
             print(f"fp32 s={s} live {len(ora['id'])} median {np.median(err):.2e} q99 {np.quantile(err, 0.99):.2e} "
                   f"q99.9 {np.quantile(err, 0.999):.2e} max {err.max():.2e} mismatch {mismatch} | "
                   f"fp64 one-rounding sensitivity median {np.median(base):.2e} q99 {np.quantile(base, 0.99):.2e}")
-            assert mismatch <= max(2, len(ora["id"]) // 200)
+            # particles absorbed or escaped in one run only: at most 1e-4 of them
+            assert mismatch <= int(1e-4 * len(ora["id"]))
             assert np.median(err) < 1e-5
             assert np.quantile(err, 0.99) <= 10 * np.quantile(base, 0.99) + 1e-6
             if s == 1:

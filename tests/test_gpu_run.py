@@ -11,8 +11,8 @@ from synthetic_inputs import WORKLOADS, scaled
 pytestmark = pytest.mark.gpu
 
 
-def _run(precision, w, steps):
-    ctx, sim = make_pair(w, precision, inject=True)
+def _run(precision, w, steps, poisson_tol=0.0):
+    ctx, sim = make_pair(w, precision, inject=True, poisson_tol=poisson_tol)
     try:
         for s in range(2):
             apic.apic_inject(ctx, 0, s)
@@ -32,7 +32,9 @@ def test_c1_full_run(precision):
     w = WORKLOADS["c1"]
     steps = w["steps"]
     print(f"c1 full run precision={precision}", flush=True)
-    t, phi, sim = _run(precision, w, steps)
+    # FP64: in-step solves to 1e-12 (the default 1e-10 leaves the field ~1e-9
+    # from the oracle's exact LU solve, which then dominates the comparison)
+    t, phi, sim = _run(precision, w, steps, 1e-12 if precision == apic.APIC_FP64 else 0.0)
     for s in range(2):
         # exact bookkeeping on the device
         assert int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
