@@ -188,6 +188,19 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n,
                 const double* x1, const double* x2,
                 const double* vR, const double* vZ, const double* vTheta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): apic_inject
+ * for explicit particles (n >= 0 host arrays as above), staged through a
+ * static device array instead of a per-call allocation.  It calls no hipMalloc,
+ * hipFree or allocating library routine.  At most 262144 particles per call
+ * (APIC_EINVAL beyond; the array, 10 MiB, is held by every GPU the library runs
+ * on until the process ends).  All calls on one GPU share that array: calls
+ * that overlap on one GPU (several host threads or contexts at once) race.
+ * Otherwise the same results and errors as apic_inject. */
+int apic_inject_noalloc(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n,
+                        const double* x1, const double* x2,
+                        const double* vR, const double* vZ, const double* vTheta);
+
 /* Advances every grain by n_steps on the context's stream.  Each step reads
  * the multigrid convergence state once (one stream synchronisation); the call
  * returns APIC_ENOMEM if injection ran out of particle slots (the particles

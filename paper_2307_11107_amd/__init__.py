@@ -93,6 +93,15 @@ def apic_inject(ctx, grain, sp, x1=None, x2=None, vR=None, vZ=None, vTheta=None)
     _check(lib().apic_inject(ctx, grain, sp, n, *[_dptr(a) for a in arrs]), ctx)
 
 
+def apic_inject_noalloc(ctx, grain, sp, x1, x2, vR, vZ, vTheta):
+    """Explicit particles (float64 arrays) staged without device allocation."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x1, x2, vR, vZ, vTheta)]
+    n = len(arrs[0])
+    if any(len(a) != n for a in arrs):
+        raise ValueError("particle arrays differ in length")
+    _check(lib().apic_inject_noalloc(ctx, grain, sp, n, *[_dptr(a) for a in arrs]), ctx)
+
+
 def apic_step(ctx, n_steps=1):
     _check(lib().apic_step(ctx, int(n_steps)), ctx)
 

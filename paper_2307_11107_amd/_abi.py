@@ -61,6 +61,7 @@ _D = C.POINTER(C.c_double)
 PROTOTYPES = {
     "apic_init": (C.c_int, [C.POINTER(apic_grain_cfg), C.c_int32, C.POINTER(apic_opts), C.POINTER(C.c_void_p)]),
     "apic_inject": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D, _D, _D]),
+    "apic_inject_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, _D, _D, _D, _D, _D]),
     "apic_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "apic_solve_poisson": (C.c_int, [C.c_void_p, C.c_int32, _D, _D]),
     "apic_tallies": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(apic_tally)]),

@@ -1162,6 +1162,11 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
         hs[i] = HostSetup();
     }
     if (rc == APIC_OK) rc = build_tables(ctx);
+    if (rc == APIC_OK && noalloc_scratch(&ctx->scratch) != hipSuccess) {
+        // only apic_inject_noalloc needs it; it reports the failure
+        (void)hipGetLastError();
+        ctx->scratch = nullptr;
+    }
     if (rc == APIC_OK) {
         // vacuum field until particles are loaded
         rc = rebuild_fields(ctx, 1e-15, 100, true, -1);
@@ -1177,57 +1182,48 @@ int apic_init(const apic_grain_cfg* cfgs, int32_t n_grains, const apic_opts* opt
     return APIC_OK;
 }
 
-int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const double* x1,
-                const double* x2, const double* vR, const double* vZ, const double* vTheta) {
-    TRY(check_grain(ctx, grain));
-    Grain& g = ctx->grains[grain];
-    if (species < 0 || species >= g.ns) return fail(ctx, APIC_EINVAL, "species index out of range");
-    const bool load = n < 0;
-    if (load && (x1 || x2 || vR || vZ || vTheta))
-        return fail(ctx, APIC_EINVAL, "n < 0 requests a volume load: arrays must be NULL");
-    if (!load && n > 0 && !(x1 && x2 && vR && vZ && vTheta))
-        return fail(ctx, APIC_EINVAL, "particle arrays must be non-NULL");
-    const int64_t count = load ? g.cfg.sp[species].n_macro : n;
-    if (count > g.capacity[species])
-        return fail(ctx, APIC_ENOMEM, "particle count exceeds the species capacity");
-    // host arrays are checked before any device work
-    for (int64_t k = 0; !load && k < count; ++k) {
+}  // extern "C"
+
+namespace {
+
+// Host-side check of explicit particles, before any device work.
+int check_particles(apic_ctx* ctx, const Grain& g, int64_t count, const double* x1, const double* x2,
+                    const double* vR, const double* vZ, const double* vTheta) {
+    for (int64_t k = 0; k < count; ++k) {
         if (!(x1[k] > -1.0 && x1[k] < g.cfg.x1_out && x2[k] >= -1.0 && x2[k] <= 1.0))
             return fail(ctx, APIC_EINVAL, "particle " + std::to_string(k) +
                                               " outside the domain (-1 < x1 < x1_out, |x2| <= 1)");
         if (!(std::isfinite(vR[k]) && std::isfinite(vZ[k]) && std::isfinite(vTheta[k])))
             return fail(ctx, APIC_EINVAL, "particle " + std::to_string(k) + " has a non-finite velocity");
     }
-    const int s = species;
-    g.cur[s] = 0;
-    if (load) {
-        if (count > 0) HIPCHK(ctx, launch_load(ctx, g, s, count));
-    } else if (count > 0) {
-        double* tmp = nullptr;
-        int* bad = nullptr;
-        TRY(alloc_t(ctx, &tmp, (size_t)5 * count));
-        if (alloc_t(ctx, &bad, 1) != APIC_OK) {
-            (void)hipFree(tmp);
-            return APIC_ENOMEM;
-        }
-        const double* src[5] = {x1, x2, vR, vZ, vTheta};
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 5 && e == hipSuccess; ++k)
-            e = hipMemcpyAsync(tmp + (size_t)k * count, src[k], sizeof(double) * count,
-                               hipMemcpyHostToDevice, ctx->stream);
-        if (e == hipSuccess) e = launch_fill(ctx, bad, sizeof(int));
-        if (e == hipSuccess)
-            e = launch_set_particles(ctx, g, s, count, tmp, tmp + count, tmp + 2 * count,
-                                     tmp + 3 * count, tmp + 4 * count, bad);
-        int hbad = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        (void)hipFree(tmp);
-        (void)hipFree(bad);
-        if (e != hipSuccess) return fail(ctx, APIC_EDEVICE, std::string("apic_inject: ") + hipGetErrorString(e));
-        if (hbad) return fail(ctx, APIC_EINVAL, "particle outside the domain (-1 < x1 < x1_out, |x2| <= 1)");
-    }
-    // counters of this species restart with the new population
+    return APIC_OK;
+}
+
+// Explicit particles through a device staging area of 5 * count doubles
+// (stage) and one flag word (bad): host -> staging copies, then k_set writes
+// them into the species' current buffer in its storage form.
+int upload_particles(apic_ctx* ctx, Grain& g, int s, int64_t count, const double* const src[5], double* stage,
+                     int* bad) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 5 && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(stage + (size_t)k * count, src[k], sizeof(double) * count, hipMemcpyHostToDevice,
+                           ctx->stream);
+    if (e == hipSuccess) e = launch_fill(ctx, bad, sizeof(int));
+    if (e == hipSuccess)
+        e = launch_set_particles(ctx, g, s, count, stage, stage + count, stage + 2 * count, stage + 3 * count,
+                                 stage + 4 * count, bad);
+    int hbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, APIC_EDEVICE, std::string("apic_inject: ") + hipGetErrorString(e));
+    if (hbad) return fail(ctx, APIC_EINVAL, "particle outside the domain (-1 < x1 < x1_out, |x2| <= 1)");
+    return APIC_OK;
+}
+
+// After a species' particles are set: its counters restart with the new
+// population, its tallies are cleared, it is sorted, and the field is due.
+int finish_inject(apic_ctx* ctx, int grain, int s, int64_t count) {
+    Grain& g = ctx->grains[grain];
     DevCounters h;
     HIPCHK(ctx, hipMemcpyAsync(&h, g.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1249,6 +1245,66 @@ int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const 
     g.field_stale = true;
     g.loaded[s] = true;
     return APIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int apic_inject(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const double* x1,
+                const double* x2, const double* vR, const double* vZ, const double* vTheta) {
+    TRY(check_grain(ctx, grain));
+    Grain& g = ctx->grains[grain];
+    if (species < 0 || species >= g.ns) return fail(ctx, APIC_EINVAL, "species index out of range");
+    const bool load = n < 0;
+    if (load && (x1 || x2 || vR || vZ || vTheta))
+        return fail(ctx, APIC_EINVAL, "n < 0 requests a volume load: arrays must be NULL");
+    if (!load && n > 0 && !(x1 && x2 && vR && vZ && vTheta))
+        return fail(ctx, APIC_EINVAL, "particle arrays must be non-NULL");
+    const int64_t count = load ? g.cfg.sp[species].n_macro : n;
+    if (count > g.capacity[species])
+        return fail(ctx, APIC_ENOMEM, "particle count exceeds the species capacity");
+    if (!load) TRY(check_particles(ctx, g, count, x1, x2, vR, vZ, vTheta));
+    const int s = species;
+    g.cur[s] = 0;
+    if (load) {
+        if (count > 0) HIPCHK(ctx, launch_load(ctx, g, s, count));
+    } else if (count > 0) {
+        double* tmp = nullptr;
+        int* bad = nullptr;
+        TRY(alloc_t(ctx, &tmp, (size_t)5 * count));
+        if (alloc_t(ctx, &bad, 1) != APIC_OK) {
+            (void)hipFree(tmp);
+            return APIC_ENOMEM;
+        }
+        const double* src[5] = {x1, x2, vR, vZ, vTheta};
+        const int rc = upload_particles(ctx, g, s, count, src, tmp, bad);
+        (void)hipFree(tmp);
+        (void)hipFree(bad);
+        TRY(rc);
+    }
+    return finish_inject(ctx, grain, s, count);
+}
+
+int apic_inject_noalloc(apic_ctx* ctx, int32_t grain, int32_t species, int64_t n, const double* x1,
+                        const double* x2, const double* vR, const double* vZ, const double* vTheta) {
+    TRY(check_grain(ctx, grain));
+    Grain& g = ctx->grains[grain];
+    if (species < 0 || species >= g.ns) return fail(ctx, APIC_EINVAL, "species index out of range");
+    if (n < 0 || n > NOALLOC_MAX_PARTICLES)
+        return fail(ctx, APIC_EINVAL, "apic_inject_noalloc takes 0 to " + std::to_string(NOALLOC_MAX_PARTICLES) +
+                                          " particles per call");
+    if (n > 0 && !(x1 && x2 && vR && vZ && vTheta)) return fail(ctx, APIC_EINVAL, "particle arrays must be non-NULL");
+    if (n > g.capacity[species]) return fail(ctx, APIC_ENOMEM, "particle count exceeds the species capacity");
+    if (!ctx->scratch) return fail(ctx, APIC_EDEVICE, "the static staging array was not found on this device");
+    TRY(check_particles(ctx, g, n, x1, x2, vR, vZ, vTheta));
+    g.cur[species] = 0;
+    if (n > 0) {
+        const double* src[5] = {x1, x2, vR, vZ, vTheta};
+        TRY(upload_particles(ctx, g, species, n, src, ctx->scratch,
+                             reinterpret_cast<int*>(ctx->scratch + 5 * NOALLOC_MAX_PARTICLES)));
+    }
+    return finish_inject(ctx, grain, species, n);
 }
 
 int apic_step(apic_ctx* ctx, int64_t n_steps) {

@@ -272,6 +272,7 @@ struct apic_ctx {
     apic::TuneState tune;
     hipGraphExec_t graph[apic::G_COUNT] = {};
     // profiling
+    double* scratch = nullptr;              // static staging array of apic_inject_noalloc
     bool profiling = false;
     bool profiled = false;                  // timing was enabled at some point
     std::vector<apic::TimerPair> timers;   // recorded, not yet harvested
@@ -295,6 +296,10 @@ hipError_t launch_set_particles(apic_ctx* ctx, Grain& g, int s, int64_t n, const
 hipError_t launch_readback(apic_ctx* ctx, Grain& g, int s, int64_t n, double* dx1, double* dx2,
                            double* dvR, double* dvZ, double* dvT, int64_t* did);
 hipError_t launch_count_live(apic_ctx* ctx, Grain& g, int s, unsigned long long* out);
+// device address of the static staging array of apic_inject_noalloc on the
+// current device (looked up once per device)
+constexpr int64_t NOALLOC_MAX_PARTICLES = 262144;
+hipError_t noalloc_scratch(double** out);
 int max_sort_blocks();
 int scan_seg_len();
 int push_chunk(bool split);

@@ -33,6 +33,7 @@
 #include "device_common.h"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 namespace apic {
@@ -1804,6 +1805,35 @@ hipError_t launch_readback(apic_ctx* ctx, Grain& g, int s, int64_t n, double* dx
     hipLaunchKernelGGL(k_readback, dim3(grid_for(ctx, n)), dim3(BLOCK), 0, ctx->stream, g.gp, s,
                        is_split(ctx), b, g.ctr, dx1, dx2, dvR, dvZ, dvT, did, cursor);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- static scratch
+// Staging of the allocation-free particle upload (apic_inject_noalloc): the
+// host arrays of at most NOALLOC_MAX_PARTICLES particles as five FP64 columns
+// (x1, x2, vR, vZ, vTheta), then one word for the out-of-domain flag.  A
+// file-scope device array: every GPU the library runs on holds its own copy
+// (10 MiB) until the process ends, and calls that overlap on one GPU race on
+// it.  In host code `scratch` names a host-side stand-in, so its device
+// address is looked up once per device and only that address is used.
+static __device__ __align__(256) double scratch[5 * NOALLOC_MAX_PARTICLES + 32];
+
+hipError_t noalloc_scratch(double** out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static double* addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_count_live(apic_ctx* ctx, Grain& g, int s, unsigned long long* out) {
