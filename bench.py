@@ -7,12 +7,16 @@ charge density, FP64 multigrid Poisson solve and nodal gradient; grain force).
 both species pushed per step, summed, divided by the wall time between two
 device synchronisations), inputs resident in HBM before timing starts.
 
-Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-[--workload c3] [--no-fp64] [--no-cpu-baseline] [--no-ensemble]
+Headline workload: c4, the batched ensemble of 64 grains in one context (the
+FP32 batched form, autotuned launch schedule, graph-captured steps).  Beside it
+the line carries the plain FP64 path on the same ensemble (`fp64`,
+`speedup_fp32_vs_fp64`), the single-grain workloads c3 (FP32 and FP64) and c5,
+the Boltzmann-electron and conservative field-solve modes on c3, and the
+oracle's rate on a bounded sample of the headline workload (`cpu_baseline`).
 
-Beside the headline workload the line carries the plain FP64 path on the same
-workload (`fp64`), the 64-grain ensemble in one context (`ensemble`), and the
-oracle's rate on a bounded sample (`cpu_baseline`).
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+[--no-fp64] [--no-cpu-baseline] [--no-c3] [--no-c5] [--no-boltzmann]
+[--no-conservative]
 """
 import argparse
 import json
@@ -25,8 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_PARTICLE = {"fp32": 48, "fp64": 80}   # read + write of the particle state
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_split_c3_traffic.md")
-TRAFFIC_WORKLOAD = "c3"
+TRAFFIC_FILES = {"c4": os.path.join(ROOT, "profiles", "k_push_split_c4_traffic.md"),
+                 "c3": os.path.join(ROOT, "profiles", "k_push_split_c3_traffic.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2307_11107_amd", "csrc", "particles.hip")
 COPY_BYTES = 1 << 30           # calibration copy: 1 GiB read + 1 GiB written
 
@@ -46,11 +50,11 @@ def copy_calibration():
 def measured_traffic(particles_per_launch, workload):
     """HBM bytes per push launch from the committed counter summary, if it was
     taken on the current kernel source and this workload (else None)."""
-    if workload != TRAFFIC_WORKLOAD:
+    if workload not in TRAFFIC_FILES:
         return None
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(TRAFFIC_FILES[workload]).read()
     except OSError:
         return None
     vals = {}
@@ -131,19 +135,47 @@ def cpu_baseline(w, n_sample, steps):
     return pushed / dt, dt
 
 
+def push_summary(r, precision):
+    """Average push launch time and algorithmic GB/s of a run."""
+    tm = r["timing"]
+    avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
+    per_launch = r["particle_steps"] / max(tm["push_launches"], 1)
+    gbs = BYTES_PER_PARTICLE[precision] * per_launch / (avg_ms * 1e-3) / 1e9
+    return avg_ms, per_launch, gbs
+
+
+def breakdown(r):
+    tm = r["timing"]
+    return {k: tm[k] / max(tm["steps"], 1) for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")}
+
+
+def secondary(r, precision, steps, workload, unit="particle-steps/s"):
+    avg, _, gbs = push_summary(r, precision)
+    tm = r["timing"]
+    return {"workload": workload, "value": r["particle_steps"] / r["elapsed"], "unit": unit,
+            "ms_per_step": 1e3 * r["elapsed"] / steps, "push_avg_launch_ms": avg, "push_GBps": gbs,
+            "push_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "breakdown_ms_per_step": breakdown(r),
+            "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1), "balance_exact": r["balance_exact"]}
+
+
+def describe(name, w):
+    return (f"{name}: alpha={w['alpha']}, wce/wpe={w['wce']}, grid {w['n1']}x{w['n2']}, x1_out={w['x1_out']}, "
+            f"lambdaD/R0={w['kappa']}, mi/me={w['mi']}, Ti/Te={w['Ti']}, {w['n_macro']:.0e} macro-particles per "
+            f"species, Maxwellian flux injection, dt={w['dt']}/wpe")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=5)
-    ap.add_argument("--no-ensemble", action="store_true")
-    ap.add_argument("--ensemble-steps", type=int, default=16)
-    ap.add_argument("--ensemble-warmup", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--c3-steps", type=int, default=50)
+    ap.add_argument("--c3-warmup", type=int, default=10)
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-boltzmann", action="store_true")
     ap.add_argument("--no-conservative", action="store_true")
@@ -156,17 +188,18 @@ def main():
         sys.exit(2)
     import torch
     from synthetic_inputs import WORKLOADS, ensemble_c4
-    w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     copy_calibration()
 
-    r32 = run_gpu([w], "fp32", args.steps, args.warmup, stream)
+    # headline: the c4 ensemble, FP32 split, autotuned (the tuner's steps are
+    # part of the warm-up)
+    ens = ensemble_c4()
+    n_ens = sum(g["n_macro"] for g in ens)
+    r32 = run_gpu(ens, "fp32", args.steps, args.warmup, stream, autotune=True)
     value = r32["particle_steps"] / r32["elapsed"]
+    push_avg_ms, per_launch, achieved = push_summary(r32, "fp32")
     tm = r32["timing"]
-    push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
-    per_launch = r32["particle_steps"] / max(tm["push_launches"], 1)
-    achieved = BYTES_PER_PARTICLE["fp32"] * per_launch / (push_avg_ms * 1e-3) / 1e9
     out = {
         "metric": "particle-steps/s (push+gather+deposit) on 1 MI355X, FP32 vs FP64; % HBM peak",
         "value": value,
@@ -180,99 +213,64 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: alpha={w['alpha']}, wce/wpe={w['wce']}, grid {w['n1']}x{w['n2']}, "
-                               f"x1_out={w['x1_out']}, lambdaD/R0={w['kappa']}, mi/me={w['mi']}, Ti/Te={w['Ti']}, "
-                               f"{w['n_macro']:.0e} macro-particles per species, Maxwellian flux injection, "
-                               f"dt={w['dt']}/wpe; FP32 split push/gather/deposit, FP64 multigrid Poisson and tallies",
-                   "particles_per_species": w["n_macro"], "grid": [w["n1"], w["n2"]]},
+        "config": {"workload": f"c4: batched ensemble of {len(ens)} grains in one context (alpha U[0,0.2], "
+                               f"wce/wpe in {{0,0.5,1}}, lambdaD/R0 U[0.5,5], grids 128x128..512x256, x1_out=-0.1, "
+                               f"mi/me=1836, Te=Ti, {n_ens:.3g} macro-particles per species in total, log-uniform "
+                               f"1e6-2e7 per grain, Maxwellian flux injection, dt=0.05/wpe); FP32 split "
+                               f"push/gather/deposit in one persistent launch, autotuned schedule, graph-captured "
+                               f"steps, FP64 multigrid Poisson and tallies",
+                   "grains": len(ens), "particles_per_species_total": n_ens},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch, args.workload),
-                     "kernel": "k_push_split (FP32 split push+gather+deposit, all species in one launch)", "avg_launch_ms": push_avg_ms,
-                     "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"]},
-        "breakdown_ms_per_step": {k: tm[k] / max(tm["steps"], 1) for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch, "c4"),
+                     "kernel": "k_push_split (FP32 split push+gather+deposit, all grains and species in one launch)",
+                     "avg_launch_ms": push_avg_ms, "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"],
+                     "particles_per_launch": per_launch},
+        "breakdown_ms_per_step": breakdown(r32),
         "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1),
+        "schedule": r32["schedule"],
         "balance_exact": r32["balance_exact"],
     }
     if not args.no_fp64:
-        r64 = run_gpu([w], "fp64", args.steps, args.warmup, stream)
+        r64 = run_gpu(ens, "fp64", args.steps, args.warmup, stream, autotune=True)
+        avg64, _, gb64 = push_summary(r64, "fp64")
         v64 = r64["particle_steps"] / r64["elapsed"]
-        t64 = r64["timing"]
-        a64 = t64["push_ms"] / max(t64["push_launches"], 1)
-        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["elapsed"] / args.steps,
-                       "push_avg_launch_ms": a64,
-                       "push_GBps": BYTES_PER_PARTICLE["fp64"] * r64["particle_steps"] / max(t64["push_launches"], 1)
-                       / (a64 * 1e-3) / 1e9}
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["elapsed"] / args.steps, "push_avg_launch_ms": avg64,
+                       "push_GBps": gb64, "breakdown_ms_per_step": breakdown(r64),
+                       "balance_exact": r64["balance_exact"]}
         out["speedup_fp32_vs_fp64"] = value / v64
-    if not args.no_ensemble:
-        ens = ensemble_c4()
-        re = run_gpu(ens, "fp32", args.ensemble_steps, args.ensemble_warmup, stream, autotune=True)
-        te = re["timing"]
-        pe = te["push_ms"] / max(te["push_launches"], 1)
-        ve = re["particle_steps"] / re["elapsed"]
-        gbe = BYTES_PER_PARTICLE["fp32"] * re["particle_steps"] / max(te["push_launches"], 1) / (pe * 1e-3) / 1e9
-        out["ensemble"] = {
-            "workload": f"c4: {len(ens)} grains in one context (alpha U[0,0.2], wce/wpe in {{0,0.5,1}}, "
-                        f"lambdaD/R0 U[0.5,5], grids 128x128..512x256, "
-                        f"{sum(g['n_macro'] for g in ens):.3g} macro-particles per species in total, "
-                        f"log-uniform 1e6-2e7 per grain), FP32 split, autotuned schedule, graph-captured steps",
-            "value": ve, "unit": "particle-steps/s", "ms_per_step": 1e3 * re["elapsed"] / args.ensemble_steps,
-            "push_avg_launch_ms": pe, "push_GBps": gbe, "push_frac_of_hbm_peak": gbe / HBM_PEAK_GBS,
-            "breakdown_ms_per_step": {k: te[k] / max(te["steps"], 1)
-                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
-            "mg_cycles_per_step": te["mg_cycles"] / max(te["steps"], 1),
-            "schedule": re["schedule"], "balance_exact": re["balance_exact"]}
-    if not args.no_c5 and args.workload != "c5":
+    if not args.no_c3:
+        w = WORKLOADS["c3"]
+        r3 = run_gpu([w], "fp32", args.c3_steps, args.c3_warmup, stream)
+        out["c3"] = secondary(r3, "fp32", args.c3_steps, describe("c3", w) + "; FP32 split")
+        out["c3"]["push_traffic"] = measured_traffic(push_summary(r3, "fp32")[1], "c3")
+        if not args.no_fp64:
+            r3d = run_gpu([w], "fp64", args.c3_steps, args.c3_warmup, stream)
+            out["c3"]["fp64"] = secondary(r3d, "fp64", args.c3_steps, describe("c3", w) + "; FP64 plain")
+            out["c3"]["speedup_fp32_vs_fp64"] = out["c3"]["value"] / out["c3"]["fp64"]["value"]
+    if not args.no_c5:
         # the largest single grain (2048 x 1024 cells, 2e8 macro-particles per
         # species): the push at four times the c3 state
         w5 = WORKLOADS["c5"]
         r5 = run_gpu([w5], "fp32", args.c5_steps, args.c5_warmup, stream)
-        t5 = r5["timing"]
-        p5 = t5["push_ms"] / max(t5["push_launches"], 1)
-        gb5 = BYTES_PER_PARTICLE["fp32"] * r5["particle_steps"] / max(t5["push_launches"], 1) / (p5 * 1e-3) / 1e9
-        out["c5"] = {
-            "workload": f"c5: alpha={w5['alpha']}, wce/wpe={w5['wce']}, grid {w5['n1']}x{w5['n2']}, "
-                        f"x1_out={w5['x1_out']}, lambdaD/R0={w5['kappa']}, {w5['n_macro']:.0e} macro-particles "
-                        f"per species, FP32 split, FP64 multigrid",
-            "value": r5["particle_steps"] / r5["elapsed"], "unit": "particle-steps/s",
-            "ms_per_step": 1e3 * r5["elapsed"] / args.c5_steps,
-            "push_avg_launch_ms": p5, "push_GBps": gb5, "push_frac_of_hbm_peak": gb5 / HBM_PEAK_GBS,
-            "breakdown_ms_per_step": {k: t5[k] / max(t5["steps"], 1)
-                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
-            "mg_cycles_per_step": t5["mg_cycles"] / max(t5["steps"], 1),
-            "balance_exact": r5["balance_exact"]}
+        out["c5"] = secondary(r5, "fp32", args.c5_steps, describe("c5", w5) + "; FP32 split, FP64 multigrid")
+    w = WORKLOADS["c3"]
     if not args.no_boltzmann:
-        # the same grain and ions with Boltzmann electrons (not moved; the
-        # field solve is the Newton-multigrid one)
-        rb = run_gpu([w], "fp32", args.steps, args.warmup, stream, boltzmann=True)
-        tb = rb["timing"]
-        pb = tb["push_ms"] / max(tb["push_launches"], 1)
-        gbb = BYTES_PER_PARTICLE["fp32"] * rb["particle_steps"] / max(tb["push_launches"], 1) / (pb * 1e-3) / 1e9
-        out["boltzmann_electrons"] = {
-            "workload": f"{args.workload} grain and ions ({w['n_macro']:.0e} macro-particles), electrons "
-                        f"n0 exp(phi) (not moved), FP32 split, FP64 Newton-multigrid Poisson",
-            "value": rb["particle_steps"] / rb["elapsed"], "unit": "ion particle-steps/s",
-            "ms_per_step": 1e3 * rb["elapsed"] / args.steps, "push_avg_launch_ms": pb, "push_GBps": gbb,
-            "push_frac_of_hbm_peak": gbb / HBM_PEAK_GBS,
-            "breakdown_ms_per_step": {k: tb[k] / max(tb["steps"], 1)
-                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
-            "mg_cycles_per_step": tb["mg_cycles"] / max(tb["steps"], 1),
-            "balance_exact": rb["balance_exact"]}
+        # the c3 grain and ions with Boltzmann electrons (not moved; the field
+        # solve is the Newton-multigrid one)
+        rb = run_gpu([w], "fp32", args.c3_steps, args.c3_warmup, stream, boltzmann=True)
+        out["boltzmann_electrons"] = secondary(
+            rb, "fp32", args.c3_steps, f"c3 grain and ions ({w['n_macro']:.0e} macro-particles), electrons "
+            f"n0 exp(phi) (not moved), FP32 split, FP64 Newton-multigrid Poisson", unit="ion particle-steps/s")
     if not args.no_conservative:
-        # the same workload with the conservative (finite-element) field solve
-        rc = run_gpu([w], "fp32", args.steps, args.warmup, stream, conservative=True)
-        tc = rc["timing"]
-        out["conservative_poisson"] = {
-            "workload": f"{args.workload}, FP32 split, field solve on the conservative (bilinear finite-element) form",
-            "value": rc["particle_steps"] / rc["elapsed"], "unit": "particle-steps/s",
-            "ms_per_step": 1e3 * rc["elapsed"] / args.steps,
-            "breakdown_ms_per_step": {k: tc[k] / max(tc["steps"], 1)
-                                      for k in ("push_ms", "inject_ms", "sort_ms", "field_ms")},
-            "mg_cycles_per_step": tc["mg_cycles"] / max(tc["steps"], 1),
-            "balance_exact": rc["balance_exact"]}
+        rc = run_gpu([w], "fp32", args.c3_steps, args.c3_warmup, stream, conservative=True)
+        out["conservative_poisson"] = secondary(
+            rc, "fp32", args.c3_steps, "c3, FP32 split, field solve on the conservative (bilinear finite-element) form")
     if not args.no_cpu_baseline:
-        rate, secs = cpu_baseline(w, args.cpu_sample, args.cpu_steps)
+        g0 = dict(ens[0])
+        rate, secs = cpu_baseline(g0, args.cpu_sample, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.workload} geometry, grid and field solve with "
+                               "sample": f"grain 0 of the c4 ensemble (alpha={g0['alpha']:.3f}, wce/wpe={g0['wce']}, "
+                                         f"grid {g0['n1']}x{g0['n2']}, lambdaD/R0={g0['kappa']:.2f}) with "
                                          f"{args.cpu_sample:.0e} macro-particles per species, {args.cpu_steps} full "
                                          f"steps ({secs:.1f} s of CPU time; numpy oracle, one thread)"}
     print(json.dumps(out))

@@ -1505,7 +1505,8 @@ __device__ inline void sort_range(int64_t n, int blocks, int64_t& lo, int64_t& h
 // all their loads issued before the first is used, so a workgroup's slot range
 // streams with many loads in flight.
 constexpr int HIST_BATCHES = 8;
-constexpr int SCATTER_BATCHES = 8;
+constexpr int SCATTER_BATCHES = 4;
+static int scatter_batch() { return SCATTER_BATCHES * BLOCK; }
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
@@ -1523,10 +1524,12 @@ k_tile_hist(const PushTask* __restrict__ tasks, int max_level) {
     sort_range(T.ctr->n[T.s], SB, lo, hi);
     for (int64_t base = lo; base < hi; base += HIST_BATCHES * BLOCK) {
         Moved<SPLIT> m[HIST_BATCHES];
+        // every load is issued (a slot past the range reloads the last one):
+        // loads behind a branch would each be waited for before the next
 #pragma unroll
         for (int k = 0; k < HIST_BATCHES; ++k) {
             const int64_t p = base + k * BLOCK + threadIdx.x;
-            if (p < hi) load_pos(b, p, m[k]);
+            load_pos(b, p < hi ? p : hi - 1, m[k]);
         }
 #pragma unroll
         for (int k = 0; k < HIST_BATCHES; ++k) {
@@ -1630,44 +1633,138 @@ k_scan_apply(const PushTask* __restrict__ tasks, int max_level) {
     }
 }
 
-// Scatter: each wave's runs of equal tiles take their offsets with one LDS
-// atomic per run.
+// 32-bit words of a moved slot, for staging in LDS.
+template <bool SPLIT> struct Words;
+template <> struct Words<true> {
+    static constexpr int N = 7;
+    static __device__ uint32_t get(const Moved<true>& m, int w) { return m.w[w]; }
+    static __device__ void set(Moved<true>& m, int w, uint32_t v) { m.w[w] = v; }
+};
+template <> struct Words<false> {
+    static constexpr int N = 11;
+    static __device__ uint32_t get(const Moved<false>& m, int w) {
+        return w < 10 ? (uint32_t)(m.d[w >> 1] >> (32 * (w & 1))) : m.id;
+    }
+    static __device__ void set(Moved<false>& m, int w, uint32_t v) {
+        if (w == 10) {
+            m.id = v;
+        } else {
+            const int sh = 32 * (w & 1);
+            m.d[w >> 1] = (m.d[w >> 1] & ~(0xFFFFFFFFull << sh)) | ((uint64_t)v << sh);
+        }
+    }
+};
+
+// Scatter, one batch of SCATTER_BATCHES * BLOCK consecutive slots at a time:
+// (1) every slot of the batch is loaded (all loads in flight together);
+// (2) a per-tile LDS counter ranks each particle within its tile in the batch,
+//     and the first particle of a tile enters the tile in the batch's list;
+// (3) the list's counts are scanned, which orders the batch by tile, and each
+//     tile takes its destination range from the workgroup's cursor;
+// (4) the particles are staged in LDS in that order and written out by
+//     consecutive threads to consecutive slots, so the stores of a wave form
+//     whole cache lines instead of one partial line per particle.
+// LDS: cursors and counters per tile (2 x ntiles ints), the batch's tile list
+// (tile, count | first, destination), and the staged words.
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
 k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
-    extern __shared__ int cur[];
+    constexpr int B = SCATTER_BATCHES * BLOCK;
+    constexpr int NW = Words<SPLIT>::N;
+    extern __shared__ int lds_i[];
+    __shared__ int nkeys, nlive;
     const PushTask& T = tasks[blockIdx.y];
     const int SB = T.sort_blocks;
     if ((int)blockIdx.x >= SB || T.sort_level > max_level) return;
     const GrainParams gp = T.gp;
     const int nt = gp.ntiles;
-    for (int t = threadIdx.x; t < nt; t += BLOCK) cur[t] = gbl(T.hist_off)[(size_t)t * SB + blockIdx.x];
+    int* cur = lds_i;                 // [ntiles] next destination slot of each tile
+    int* cnt = cur + nt;              // [ntiles] batch count (low 16 bits) | list index + 1 (high bits)
+    int* keys = cnt + nt;             // [B] the batch's tiles, in order of first appearance
+    int* first = keys + B;            // [B] their first position in tile order
+    int* dest = first + B;            // [B] their first destination slot
+    uint32_t* stage = reinterpret_cast<uint32_t*>(dest + B);   // [NW][B]
+    for (int t = threadIdx.x; t < nt; t += BLOCK) {
+        cur[t] = gbl(T.hist_off)[(size_t)t * SB + blockIdx.x];
+        cnt[t] = 0;
+    }
+    if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
     const int which = T.ctr->cur[T.s];
     const PBuf src = T.buf[which];
     const PBuf dst = T.buf[1 - which];
-    const int lane = threadIdx.x & 63;
     int64_t lo, hi;
     sort_range(T.ctr->n[T.s], SB, lo, hi);
-    for (int64_t base = lo; base < hi; base += SCATTER_BATCHES * BLOCK) {
+    for (int64_t base = lo; base < hi; base += B) {
         Moved<SPLIT> m[SCATTER_BATCHES];
+        // every load is issued (a slot past the range reloads the last one)
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
             const int64_t p = base + k * BLOCK + threadIdx.x;
-            if (p < hi) load_moved(src, p, m[k]);
+            load_moved(src, p < hi ? p : hi - 1, m[k]);
         }
+        int key[SCATTER_BATCHES], rank[SCATTER_BATCHES];
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
             const int64_t p = base + k * BLOCK + threadIdx.x;
-            const int key = p < hi ? tile_key(gp, m[k]) : -1;
-            int head, len;
-            bool is_head;
-            wave_runs(key, head, len, is_head);
-            int start = 0;
-            if (is_head && key >= 0) start = atomicAdd(&cur[key], len);
-            const int64_t o = (int64_t)__shfl(start, head) + (lane - head);
-            if (key >= 0) store_moved(dst, o, m[k]);
+            key[k] = p < hi ? tile_key(gp, m[k]) : -1;
+            rank[k] = 0;
+            if (key[k] >= 0) {
+                const int old = atomicAdd(&cnt[key[k]], 1);
+                rank[k] = old & 0xFFFF;
+                if (rank[k] == 0) {
+                    const int idx = atomicAdd(&nkeys, 1);
+                    keys[idx] = key[k];
+                    atomicOr(&cnt[key[k]], (idx + 1) << 16);
+                }
+            }
         }
+        __syncthreads();
+        // scan of the listed tiles' counts (one wave); destinations from the cursors
+        const int nk = nkeys;
+        if (threadIdx.x < 64) {
+            int run = 0;
+            for (int i0 = 0; i0 < nk; i0 += 64) {
+                const int i = i0 + (int)threadIdx.x;
+                const int c = i < nk ? (cnt[keys[i]] & 0xFFFF) : 0;
+                int x = c;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o);
+                    if ((int)threadIdx.x >= o) x += y;
+                }
+                if (i < nk) {
+                    first[i] = run + x - c;
+                    dest[i] = cur[keys[i]];
+                    cur[keys[i]] += c;
+                }
+                run += __shfl(x, 63);
+            }
+            if (threadIdx.x == 0) nlive = run;
+        }
+        __syncthreads();
+        // stage in tile order
+#pragma unroll
+        for (int k = 0; k < SCATTER_BATCHES; ++k) {
+            if (key[k] < 0) continue;
+            const int pos = first[(cnt[key[k]] >> 16) - 1] + rank[k];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) stage[w * B + pos] = Words<SPLIT>::get(m[k], w);
+        }
+        __syncthreads();
+        // consecutive threads write consecutive staged particles
+        const int live = nlive;
+        for (int q = threadIdx.x; q < live; q += BLOCK) {
+            Moved<SPLIT> mm;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) Words<SPLIT>::set(mm, w, stage[w * B + q]);
+            const int idx = (cnt[tile_key(gp, mm)] >> 16) - 1;
+            store_moved(dst, (int64_t)dest[idx] + (q - first[idx]), mm);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nk; i += BLOCK) cnt[keys[i]] = 0;
+        if (threadIdx.x == 0) nkeys = 0;
+        __syncthreads();
     }
 }
 
@@ -1766,6 +1863,9 @@ hipError_t launch_inject(apic_ctx* ctx, bool deposit) {
 hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks, int max_level) {
     const bool split = is_split(ctx);
     const size_t lds = sizeof(int) * (size_t)ctx->max_ntiles;
+    // scatter: cursors and counters per tile, the batch's tile list and its staged words
+    const size_t lds_scatter = sizeof(int) * (2 * (size_t)ctx->max_ntiles + 3 * (size_t)scatter_batch()) +
+                               sizeof(uint32_t) * (size_t)(split ? 7 : 11) * scatter_batch();
     const PushTask* t = ctx->tasks + first_task;
     const dim3 sgrid(ctx->max_sort_blocks, n_tasks);
     const dim3 cgrid(ctx->max_segs, n_tasks);
@@ -1774,8 +1874,8 @@ hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks, int max_level
     hipLaunchKernelGGL(k_scan_reduce, cgrid, dim3(BLOCK), 0, ctx->stream, t, max_level);
     hipLaunchKernelGGL(k_scan_segs, dim3(n_tasks), dim3(1024), 0, ctx->stream, t, max_level);
     hipLaunchKernelGGL(k_scan_apply, cgrid, dim3(BLOCK), 0, ctx->stream, t, max_level);
-    if (split) hipLaunchKernelGGL(k_tile_scatter<true>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
-    else hipLaunchKernelGGL(k_tile_scatter<false>, sgrid, dim3(BLOCK), lds, ctx->stream, t, max_level);
+    if (split) hipLaunchKernelGGL(k_tile_scatter<true>, sgrid, dim3(BLOCK), lds_scatter, ctx->stream, t, max_level);
+    else hipLaunchKernelGGL(k_tile_scatter<false>, sgrid, dim3(BLOCK), lds_scatter, ctx->stream, t, max_level);
     hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(BLOCK), 0, ctx->stream, t, n_tasks, max_level);
     return hipGetLastError();
 }
