@@ -158,7 +158,12 @@ int read_batch(apic_ctx* ctx, MGBatch& b) {
 // boundary coupling, D the operator's diagonal); standalone solves (to_floor)
 // also stop at stagnation.  In-step solves replay the captured V-cycle as many
 // times as the previous solve needed before reading the convergence state once
-// (cycles after convergence do nothing on the device).
+// (cycles after convergence do nothing on the device).  Only the last two of
+// those predicted cycles end with the residual norm and the check (two of the
+// ~10 latency-bound launches of a cycle): the check before the last tells
+// whether one cycle fewer would have done, and the prediction drops by one.
+// Grains that converged earlier keep cycling until then, which only lowers
+// their residual further.
 int solve_linear(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int only, bool in_step, int* cycles) {
     MGBatch b;
     int launched = 0;
@@ -170,15 +175,19 @@ int solve_linear(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int o
             (void)mg_begin(ctx, tol, -1, true);
         }));
         const int pred = std::min(ctx->pred_cycles, max_cycles);
-        for (; launched < pred; ++launched)
-            TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
+        for (; launched < pred; ++launched) {
+            const bool check = launched + 2 >= pred;
+            TRY(run_phase(ctx, check ? G_VC : G_VCN, [&] { (void)mg_vcycle_launches(ctx, tol, check); }));
+        }
         TRY(read_batch(ctx, b));
+        const bool one_fewer = pred >= 2 && b.pending == 0 && b.pending_prev == 0;
         while (b.pending > 0 && launched < max_cycles) {
             TRY(run_phase(ctx, G_VC, [&] { (void)mg_vcycle_launches(ctx, tol); }));
             ++launched;
             TRY(read_batch(ctx, b));
         }
-        ctx->pred_cycles = b.max_cycles;
+        ctx->pred_cycles = one_fewer ? pred - 1 : launched;
+        if (cycles) *cycles = launched;
         if (b.pending > 0) {
             // stopped at the cycle cap: counted per grain, reported in the tallies
             const int G = (int)ctx->grains.size();
@@ -214,7 +223,7 @@ int solve_linear(apic_ctx* ctx, double tol, int max_cycles, bool to_floor, int o
         HIPCHK(ctx, launch_fill(ctx, &ctx->mgb->nan, sizeof(int)));
         return fail(ctx, APIC_EDEVICE, "Poisson solve produced NaN");
     }
-    if (cycles) *cycles = b.max_cycles;
+    if (cycles && !in_step) *cycles = b.max_cycles;
     return APIC_OK;
 }
 

@@ -154,7 +154,7 @@ struct MGBatch {
     int pending;                // grains not yet converged
     int nan;                    // a residual was not finite
     int max_cycles;             // largest cycles count of this solve
-    int pad;
+    int pending_prev;           // `pending` of the check before the last one
 };
 
 struct MGLevel {
@@ -227,7 +227,8 @@ struct TimerPair { hipEvent_t a, b; int kind; };
 // (88^2 doubles and the pivot scratch stay within 64 KiB)
 constexpr int BOLTZ_INV_MAX = 88;
 constexpr int SORT_LEVELS = 5;   // a slow species is sorted up to 16x less often
-enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_POST, G_NEWTON, G_NEWTON_NEXT, G_SORT, G_COUNT = G_SORT + SORT_LEVELS };
+enum GraphId { G_PUSH = 0, G_INJ, G_PRE, G_VC, G_VCN, G_POST, G_NEWTON, G_NEWTON_NEXT, G_SORT,
+               G_COUNT = G_SORT + SORT_LEVELS };
 
 }  // namespace apic
 
@@ -320,6 +321,6 @@ hipError_t mg_extrapolate(apic_ctx* ctx);
 hipError_t newton_prepare(apic_ctx* ctx, int only, bool invert);
 hipError_t newton_limit(apic_ctx* ctx, int only);
 hipError_t mg_begin(apic_ctx* ctx, double tol, int only_grain, bool in_step);
-hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol);
+hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol, bool check = true);
 
 }  // namespace apic

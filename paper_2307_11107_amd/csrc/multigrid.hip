@@ -598,6 +598,7 @@ __global__ void __launch_bounds__(MG_BLOCK)
 k_residual_norm(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, double* __restrict__ part,
                 MGBatch* __restrict__ mb) {
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        mb->pending_prev = mb->pending;
         mb->pending = 0;
         mb->max_cycles = 0;
     }
@@ -1330,8 +1331,8 @@ hipError_t mg_extrapolate(apic_ctx* ctx) {
 
 // One V-cycle (sawtooth: restriction of the current residual down to the
 // coarsest level, then correction and smoothing on the way up) of every grain
-// not yet done, then the residual norm and the check.
-hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
+// not yet done, then (check) the residual norm and the convergence check.
+hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol, bool check) {
     const int G = (int)ctx->grains.size();
     const int nl = ctx->n_levels;
     coarse_solve(ctx, 0);
@@ -1350,7 +1351,7 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol) {
         coarse_solve(ctx, l + 1);
     }
     for (int l = nl - 2; l >= 0; --l) smooth(ctx, l);   // correction applied by the first sweep
-    residual_check(ctx, tol, 1, false);
+    if (check) residual_check(ctx, tol, 1, false);
     return hipGetLastError();
 }
 

@@ -145,14 +145,16 @@ __device__ __attribute__((noinline)) T chord_hit(T rho_max, T alpha, T R, T Z, T
 }
 
 // Chord test of a step: -1 unless the chord comes within rho_max of the
-// origin (the usual case, decided here without the search).
+// origin (the usual case, decided here without the search).  The squared
+// distance of the chord's closest point, m = clamp(-P.d, 0, |d|^2) along it,
+// times |d|^2 is |P|^2 |d|^2 - m (2 (-P.d) - m): no division.
 template <typename T>
 __device__ inline T grain_chord(T rho_max, T alpha, T R, T Z, T dX, T dY, T dZ, int iters) {
     const T dd = dX * dX + dY * dY + dZ * dZ;
     const T pd = -(R * dX + Z * dZ);
-    const T tc = pd > T(0) ? (pd < dd ? pd / dd : T(1)) : T(0);
-    const T Xc = R + tc * dX, Yc = tc * dY, Zc = Z + tc * dZ;
-    if (Xc * Xc + Yc * Yc + Zc * Zc > rho_max * rho_max) return T(-1);
+    const T m = pd > T(0) ? (pd < dd ? pd : dd) : T(0);
+    const T c = R * R + Z * Z;
+    if (c * dd - m * (T(2) * pd - m) > rho_max * rho_max * dd) return T(-1);
     return chord_hit<T>(rho_max, alpha, R, Z, dX, dY, dZ, iters);
 }
 
