@@ -816,6 +816,10 @@ int build_tables(apic_ctx* ctx) {
             d.alpha = g.gp.alpha;
             d.h1 = g.gp.h1 * (double)(1 << l);
             d.h2 = g.gp.h2 * (double)(1 << l);
+            d.ih1sq = 1.0 / (d.h1 * d.h1);
+            d.ih2sq = 1.0 / (d.h2 * d.h2);
+            d.i2h2 = 1.0 / (2.0 * d.h2);
+            d.i4h1h2 = 1.0 / (4.0 * d.h1 * d.h2);
             d.u = L.u;
             d.f = L.f;
             d.uT = L.uT;

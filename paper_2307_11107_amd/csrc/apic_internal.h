@@ -127,6 +127,7 @@ struct MGDesc {
     int coarsest;               // this is the grain's last level (dense solve)
     int m;                      // nodes of the dense system (coarsest only)
     double alpha, h1, h2;       // finest level: geometry of its stencil (evaluated at the nodes)
+    double ih1sq, ih2sq, i2h2, i4h1h2;   // 1/h1^2, 1/h2^2, 1/(2 h2), 1/(4 h1 h2)
     const double* st;           // stored levels: [node * ST_STRIDE + k], k = ST_C .. ST_NE
     double* u;
     double* f;

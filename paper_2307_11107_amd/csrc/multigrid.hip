@@ -36,12 +36,24 @@ __device__ inline double rcp64(double x) {
 // Parallel cyclic reduction on a set of tridiagonal systems held in LDS (a:
 // sub, b: diagonal, c: super, d: rhs).  Equation e belongs to system e / L and
 // couples only inside its system; a[first] = c[last] = 0.  Each thread owns up
-// to K equations.  On return d[e] / b[e] is the solution.
+// to K equations and keeps their diagonals in registers; the LDS array b holds
+// the reciprocals of the diagonals (Newton-refined, one per equation and step,
+// read by both neighbours).  On return d[e] * b[e] is the solution.
 template <int K, int NT>
 __device__ __forceinline__ void pcr_solve(double* a, double* b, double* c, double* d, int L, int total) {
     int jj[K];
+    double bb[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) jj[k] = (threadIdx.x + k * NT) % L;
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + k * NT;
+        jj[k] = e % L;
+        bb[k] = 1.0;
+        if (e < total) {
+            bb[k] = b[e];
+            b[e] = rcp64(bb[k]);
+        }
+    }
+    __syncthreads();
     for (int s = 1; s < L; s <<= 1) {
         double na[K], nb[K], nc[K], nd[K];
 #pragma unroll
@@ -49,16 +61,16 @@ __device__ __forceinline__ void pcr_solve(double* a, double* b, double* c, doubl
             const int e = threadIdx.x + k * NT;
             if (e < total) {
                 const int j = jj[k];
-                double ai = a[e], bi = b[e], ci = c[e], di = d[e];
+                double ai = a[e], bi = bb[k], ci = c[e], di = d[e];
                 double an = 0.0, cn = 0.0;
                 if (j - s >= 0) {
-                    const double m = ai * rcp64(b[e - s]);
+                    const double m = ai * b[e - s];
                     bi -= m * c[e - s];
                     di -= m * d[e - s];
                     an = -m * a[e - s];
                 }
                 if (j + s < L) {
-                    const double m = ci * rcp64(b[e + s]);
+                    const double m = ci * b[e + s];
                     bi -= m * a[e + s];
                     di -= m * d[e + s];
                     cn = -m * c[e + s];
@@ -75,7 +87,8 @@ __device__ __forceinline__ void pcr_solve(double* a, double* b, double* c, doubl
             const int e = threadIdx.x + k * NT;
             if (e < total) {
                 a[e] = na[k];
-                b[e] = nb[k];
+                bb[k] = nb[k];
+                b[e] = rcp64(nb[k]);
                 c[e] = nc[k];
                 d[e] = nd[k];
             }
@@ -147,8 +160,8 @@ __device__ __forceinline__ void tri_solve(double* a, double* b, double* c, doubl
     d[r0 + 1] = ld;
     __syncthreads();
     pcr_solve<2, NT>(a, b, c, d, 2 * NT, 2 * NT);
-    const double y0 = d[r0] * rcp64(b[r0]);
-    const double yl = d[r0 + 1] * rcp64(b[r0 + 1]);
+    const double y0 = d[r0] * b[r0];
+    const double yl = d[r0 + 1] * b[r0 + 1];
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -198,23 +211,26 @@ struct StoredStencil {
 };
 
 // Finest level: the central differences of eq. (7) evaluated at the node
-// (r from eq. 3, second-order one-sided d/dx2 on the axis rows), the same
+// (r from eq. 3, second-order one-sided d/dx2 on the axis rows), the
 // expressions the host uses to build the hierarchy.  Nothing is read from
 // memory, which removes 72 bytes per node from every sweep of the largest
-// level.
+// level.  The reciprocals of the grid spacings come from the level's
+// descriptor and the two per-node divisions are Newton-refined reciprocals
+// (within an ulp of the host's quotients; the FP64 divisions were a large
+// part of these kernels' instructions on many-grain ensembles).
 struct FineStencil {
     double a, h1, h2, ih1sq, ih2sq, i2h2, i4h1h2;
     const double* sh;
     int n2;
     __device__ explicit FineStencil(const MGDesc& D)
-        : a(D.alpha), h1(D.h1), h2(D.h2), ih1sq(1.0 / (D.h1 * D.h1)), ih2sq(1.0 / (D.h2 * D.h2)),
-          i2h2(1.0 / (2.0 * D.h2)), i4h1h2(1.0 / (4.0 * D.h1 * D.h2)), sh(D.shift), n2(D.n2) {}
+        : a(D.alpha), h1(D.h1), h2(D.h2), ih1sq(D.ih1sq), ih2sq(D.ih2sq), i2h2(D.i2h2), i4h1h2(D.i4h1h2),
+          sh(D.shift), n2(D.n2) {}
     __device__ Coef at(int j, int i, size_t o) const {
         const double x1 = -1.0 + i * h1, x2 = -1.0 + j * h2;
-        const double r = -(1.0 + sqrt(1.0 - 4.0 * a * x1 * x2)) / (2.0 * x1);
+        const double r = (1.0 + sqrt(1.0 - 4.0 * a * x1 * x2)) * rcp64(-2.0 * x1);
         const bool edge = (j == 0 || j == n2);
         const double s2 = edge ? 0.0 : 1.0 - x2 * x2;
-        const double ir2 = 1.0 / (r * r);
+        const double ir2 = rcp64(r * r);
         const double t = r + 2.0 * a * x2;
         const double a11 = (t * t + a * a * s2) * (ir2 * ir2 * ir2) * ih1sq;
         const double c2 = -2.0 * x2 * ir2;
@@ -382,7 +398,7 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     }
     __syncthreads();
     pcr_solve<K, NT>(a, b, c, d, L, L);
-    for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * rcp64(b[k]);
+    for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * b[k];
     }
 }
 
@@ -464,7 +480,7 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
         const int i = i0 + 2 * m;
         if (i > n1 - 1) continue;
         const int e = m * L + j;
-        u[(size_t)j * nx + i] = d[e] * rcp64(b[e]);
+        u[(size_t)j * nx + i] = d[e] * b[e];
     }
 }
 
