@@ -377,23 +377,20 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
     // boundaries: absorbed if the chord meets the grain (or, by rounding next
     // to the surface, only the end point lies inside: tallied there)
     const float t_hit = grain_chord<float>((float)gp.r_grain_max, alpha, R, Z, dX, dY, dZ, 24);
-    if (i1n < 0 || t_hit >= 0.f) {
+    const bool absorbed = i1n < 0 || t_hit >= 0.f;
+    if (absorbed)
         tally_impact<float>(gp.n_bins, ImpactSpecies{sp.q, sp.m, sp.w, sp.e_bind}, s, ns, R, Z, dX,
                             dY, dZ, t_hit >= 0.f ? t_hit : 1.f, vR, vZ, vT, tally, tally_count);
-        *cell = DEAD;
-        return 1;
-    }
-    if (i1n >= n1) {
-        *cell = DEAD;
-        return 2;
-    }
-    st_stream(cell, pack_cell(i1n, i2n));
+    const int res = absorbed ? 1 : (i1n >= n1 ? 2 : 0);
+    // every slot is written, a removed particle with the dead mark (its other
+    // words are not read again): the stores need no branch
+    st_stream(cell, res == 0 ? pack_cell(i1n, i2n) : DEAD);
     st_stream(slot4(static_cast<float*>(b.pos1), p), f1n);
     st_stream(slot4(static_cast<float*>(b.pos2), p), f2n);
     st_stream(slot4(static_cast<float*>(b.vR), p), vRn);
     st_stream(slot4(static_cast<float*>(b.vZ), p), vZ);
     st_stream(slot4(static_cast<float*>(b.vT), p), vTn);
-    return 0;
+    return res;
 }
 
 // ----------------------------------------------------------------- FP64 plain push
