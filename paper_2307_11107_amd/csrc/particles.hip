@@ -198,6 +198,7 @@ __device__ __attribute__((noinline)) void tally_impact(int n_bins, ImpactSpecies
 // only by ~1e-7 of itself.
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // One particle of the FP32 split form.  Returns -1 for a dead slot, 0 if the
 // particle stays (new cell and offsets in i1n, i2n, f1n, f2n), 1 if absorbed,
@@ -327,12 +328,13 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
     const float dX = step * vR, dY = step * vT, dZ = step * vZ;
     const float X = R + dX, Zn = Z + dZ;
     const float Rn2 = X * X + dY * dY;
-    const float Rn = fsqrt(Rn2);
     // rotation of (v_R, v_Theta) into the new meridional plane, again as
-    // v + ((cos - 1) v + sin v_perp) with cos - 1 = -dY^2 / (R' (X + R'))
+    // v + ((cos - 1) v + sin v_perp) with cos - 1 = -dY^2 / (R' (X + R'));
+    // 1/R' and R' come from one reciprocal square root
     float cm = 0.f, sr = 0.f;
-    if (Rn > 0.f) {
-        const float iR = frcp(Rn);
+    if (Rn2 > 0.f) {
+        const float iR = frsq(Rn2);
+        const float Rn = Rn2 * iR;
         sr = dY * iR;
         cm = X > 0.f ? -(dY * dY) * iR * frcp(X + Rn) : X * iR - 1.f;
     }
@@ -341,9 +343,11 @@ __device__ inline int push_split_one(const GrainParams& gp, const SpeciesParams&
 
     // new conforming position from the displacement
     const float dr2 = 2.f * (R * dX + Z * dZ) + (dX * dX + dY * dY + dZ * dZ);  // r'^2 - r^2
-    const float rn = fsqrt(Rn2 + Zn * Zn);
+    const float rn2 = Rn2 + Zn * Zn;
+    const float irn = frsq(rn2);
+    const float rn = rn2 * irn;
     const float dr = dr2 * frcp(rn + r);
-    const float irr = frcp(r * rn);
+    const float irr = ir * irn;
     const float dx2 = (dZ * r - Z * dr) * irr;
     const float dx1 = dr * irr - alpha * (dx2 * r * r - x2 * dr * (2.f * r + dr)) * irr * irr;
     const float t1 = f1 + dx1 * K.ih1;
@@ -591,38 +595,65 @@ __device__ inline int find_task(const int64_t* __restrict__ prefix, int ntasks, 
     return lo;
 }
 
-__device__ inline void block_reduce7(int v[7], int (*red)[BLOCK / 64]) {
-    // v: min i1, max i1, min i2, max i2, count, sum i1, sum i2
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        v[0] = min(v[0], __shfl_xor(v[0], o));
-        v[1] = max(v[1], __shfl_xor(v[1], o));
-        v[2] = min(v[2], __shfl_xor(v[2], o));
-        v[3] = max(v[3], __shfl_xor(v[3], o));
-        v[4] += __shfl_xor(v[4], o);
-        v[5] += __shfl_xor(v[5], o);
-        v[6] += __shfl_xor(v[6], o);
-    }
+// Bounding box of a chunk's cells, held as two packed cell words (the key
+// layout, i2 << 16 | i1): the componentwise 16-bit minimum and maximum.  The
+// empty box is lo = all ones, hi = 0; a dead key (all ones) leaves the minimum
+// as it is and is masked out of the maximum.
+using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pk_min16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ inline uint32_t pk_max16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+
+struct Box {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+};
+__device__ inline void box_add(Box& b, int32_t c) {
+    b.lo = pk_min16(b.lo, (uint32_t)c);
+    b.hi = pk_max16(b.hi, c < 0 ? 0u : (uint32_t)c);
+}
+
+// Over the wave: within each row of 16 lanes by DPP (the quad swaps [1,0,3,2]
+// and [2,3,0,1], then row rotations by 4 and 8 lanes), across the four rows by
+// two xor shuffles.  Called with every lane active.
+template <bool MAX>
+__device__ inline uint32_t wave_box(uint32_t x) {
+    auto op = [](uint32_t a, uint32_t b) { return MAX ? pk_max16(a, b) : pk_min16(a, b); };
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false));
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));
+    x = op(x, (uint32_t)__shfl_xor((int)x, 16));
+    x = op(x, (uint32_t)__shfl_xor((int)x, 32));
+    return x;
+}
+
+__device__ inline Box block_box(Box b, uint32_t (*red)[BLOCK / 64]) {
+    b.lo = wave_box<false>(b.lo);
+    b.hi = wave_box<true>(b.hi);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int k = 0; k < 7; ++k) red[k][w] = v[k];
-    __syncthreads();
-    for (int k = 0; k < 7; ++k) v[k] = red[k][0];
-    for (int q = 1; q < BLOCK / 64; ++q) {
-        v[0] = min(v[0], red[0][q]);
-        v[1] = max(v[1], red[1][q]);
-        v[2] = min(v[2], red[2][q]);
-        v[3] = max(v[3], red[3][q]);
-        v[4] += red[4][q];
-        v[5] += red[5][q];
-        v[6] += red[6][q];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = b.lo;
+        red[1][w] = b.hi;
     }
     __syncthreads();
+    b.lo = red[0][0];
+    b.hi = red[1][0];
+    for (int q = 1; q < BLOCK / 64; ++q) {
+        b.lo = pk_min16(b.lo, red[0][q]);
+        b.hi = pk_max16(b.hi, red[1][q]);
+    }
+    __syncthreads();
+    return b;
 }
 
 // Deposit window of one chunk: the bounding box of the chunk's current cells
 // widened by WIN_MARGIN cells on every side (clipped to the grid), or, if that
-// exceeds the LDS capacity, a 64-column window around the chunk's mean cell.
+// exceeds the LDS capacity, a 64-column window around the box's centre.
 // Particles whose new cell falls outside go straight to global atomics.
 struct Window {
     int wi0, wj0, W, H, C;   // first node, extent in nodes, lane-striped copies
@@ -643,22 +674,24 @@ __device__ inline bool state_cell(const GrainParams& gp, const PlainState& q, in
     return true;
 }
 
-// Window from the reduced bounding box v (see block_reduce7).
-__device__ inline Window window_from(const GrainParams& gp, int v[7], int (*red)[BLOCK / 64]) {
-    block_reduce7(v, red);
+// Window from the chunk's bounding box (each lane's part in b).
+__device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*red)[BLOCK / 64]) {
+    b = block_box(b, red);
+    const int i1a = cell_i1((int32_t)b.lo), i1b = cell_i1((int32_t)b.hi);
+    const int i2a = cell_i2((int32_t)b.lo), i2b = cell_i2((int32_t)b.hi);
     Window w;
-    w.on = v[4] > 0;
+    w.on = i1a <= i1b;
     if (!w.on) return w;
     const int nx = gp.nx, ny = gp.n2 + 1;
-    w.wi0 = max(v[0] - WIN_MARGIN, 0);
-    w.wj0 = max(v[2] - WIN_MARGIN, 0);
-    w.W = min(v[1] + WIN_MARGIN + 1, gp.n1) - w.wi0 + 1;
-    w.H = min(v[3] + WIN_MARGIN + 1, gp.n2) - w.wj0 + 1;
+    w.wi0 = max(i1a - WIN_MARGIN, 0);
+    w.wj0 = max(i2a - WIN_MARGIN, 0);
+    w.W = min(i1b + WIN_MARGIN + 1, gp.n1) - w.wi0 + 1;
+    w.H = min(i2b + WIN_MARGIN + 1, gp.n2) - w.wj0 + 1;
     if (w.W * w.H > WIN_CAP) {
         w.W = min(w.W, 64);
         w.H = min(w.H, WIN_CAP / w.W);
-        w.wi0 = max(0, min(v[5] / v[4] - w.W / 2, nx - w.W));
-        w.wj0 = max(0, min(v[6] / v[4] - w.H / 2, ny - w.H));
+        w.wi0 = max(0, min((i1a + i1b) / 2 - w.W / 2, nx - w.W));
+        w.wj0 = max(0, min((i2a + i2b) / 2 - w.H / 2, ny - w.H));
     }
     // Up to 16 lane-striped copies of every window node (copy = lane mod C; the
     // copies of a node sit in consecutive LDS banks): particles of one wave
@@ -670,21 +703,14 @@ __device__ inline Window window_from(const GrainParams& gp, int v[7], int (*red)
 }
 
 template <typename S, int PB>
-__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], int (*red)[BLOCK / 64]) {
-    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
+__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], uint32_t (*red)[BLOCK / 64]) {
+    Box b;
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
         int i1, i2;
-        if (!state_cell(gp, st[k], i1, i2)) continue;
-        v[0] = min(v[0], i1);
-        v[1] = max(v[1], i1);
-        v[2] = min(v[2], i2);
-        v[3] = max(v[3], i2);
-        v[4] += 1;
-        v[5] += i1;
-        v[6] += i2;
+        if (state_cell(gp, st[k], i1, i2)) box_add(b, pack_cell(i1, i2));
     }
-    return window_from(gp, v, red);
+    return window_from(gp, b, red);
 }
 
 // FP64 form: one double per node copy.
@@ -916,22 +942,19 @@ __device__ inline void set_key(PlainState& q, const PlainKey& k) {
     q.x2 = k.x2;
 }
 
+// a split key is the packed cell itself (dead: all ones)
+__device__ inline void box_key(const GrainParams&, const SplitKey& k, Box& b) { box_add(b, k.c); }
+__device__ inline void box_key(const GrainParams& gp, const PlainKey& k, Box& b) {
+    int i1, i2;
+    if (key_cell(gp, k, i1, i2)) box_add(b, pack_cell(i1, i2));
+}
+
 template <typename K, int PB>
-__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], int (*red)[BLOCK / 64]) {
-    int v[7] = {0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff, 0, 0, 0};
+__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], uint32_t (*red)[BLOCK / 64]) {
+    Box b;
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-        int i1, i2;
-        if (!key_cell(gp, key[k], i1, i2)) continue;
-        v[0] = min(v[0], i1);
-        v[1] = max(v[1], i1);
-        v[2] = min(v[2], i2);
-        v[3] = max(v[3], i2);
-        v[4] += 1;
-        v[5] += i1;
-        v[6] += i2;
-    }
-    return window_from(gp, v, red);
+    for (int k = 0; k < PB; ++k) box_key(gp, key[k], b);
+    return window_from(gp, b, red);
 }
 
 template <bool SPLIT> struct KeyOf;
@@ -949,7 +972,7 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
     constexpr int PB = Tr::PB;
     constexpr int CHUNK = PB * BLOCK;
     __shared__ A win[WIN_CAP];
-    __shared__ int red[7][BLOCK / 64];
+    __shared__ uint32_t red[2][BLOCK / 64];
     for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
@@ -1057,7 +1080,7 @@ k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix
     constexpr int PB = Tr::PB;
     constexpr int CHUNK = PB * BLOCK;
     __shared__ A win[WIN_CAP];
-    __shared__ int red[7][BLOCK / 64];
+    __shared__ uint32_t red[2][BLOCK / 64];
     for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
