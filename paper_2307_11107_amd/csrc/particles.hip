@@ -39,13 +39,18 @@
 namespace apic {
 
 constexpr int BLOCK = 256;
+// Workgroup of the persistent push and deposit kernels: eight waves, two
+// workgroups per compute unit at four waves per SIMD.  A chunk of PB * 512
+// particles shares one deposit window, so a particle pays half the window
+// flushes and chunk-start barriers of a 256-thread workgroup.
+constexpr int PUSH_BLOCK = 512;
 constexpr double FP64_DEAD = 1.0;   // x1 of a dead FP64 slot (valid x1 < 0)
 
 __device__ inline void atomic_add_f64(double* p, double v) { gadd(p, v); }
 
 // Block-wide sum of a per-thread u32 followed by one atomic per block.
 __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
-    __shared__ uint32_t red[BLOCK / 64];
+    __shared__ uint32_t red[(BLOCK > PUSH_BLOCK ? BLOCK : PUSH_BLOCK) / 64];
     uint32_t w = v;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
@@ -528,14 +533,14 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
 
 // ----------------------------------------------------------------- ensemble push
 // One persistent launch pushes every (grain, species) task of the context.  The
-// tasks' particle slots are cut into chunks of PB * BLOCK consecutive
+// tasks' particle slots are cut into chunks of PB * PUSH_BLOCK consecutive
 // (tile-sorted) particles; k_plan_chunks lays the chunks of all tasks end to
 // end.  The chunk range is split into eight contiguous parts, one per XCD
 // (workgroup b runs on XCD b mod 8), so that the chunks of neighbouring tiles,
 // which read the same field nodes and add into the same deposit nodes, share
-// one L2.  A workgroup loads the whole state of its chunk into registers
-// first (all loads in flight together), derives the chunk's deposit window
-// from the loaded cells, then advances the particles and deposits their
+// one L2.  A workgroup loads the packed cells of its chunk first, derives the
+// chunk's deposit window from them, then advances the particles (each one's
+// state loading while the one before it is advanced) and deposits their
 // charge into an LDS window of nodes; the window's non-zero nodes are added to
 // the global deposit array once per chunk.
 template <bool SPLIT> struct PushTraits;
@@ -555,7 +560,7 @@ template <> struct PushTraits<false> {
 constexpr int WIN_CAP = 4096;
 constexpr int WIN_MARGIN = 4;
 
-int push_chunk(bool split) { return BLOCK * (split ? PushTraits<true>::PB : PushTraits<false>::PB); }
+int push_chunk(bool split) { return PUSH_BLOCK * (split ? PushTraits<true>::PB : PushTraits<false>::PB); }
 
 // chunks of every task, laid end to end: prefix[t] = first chunk of task t
 __global__ void __launch_bounds__(BLOCK)
@@ -632,7 +637,7 @@ __device__ inline uint32_t wave_box(uint32_t x) {
     return x;
 }
 
-__device__ inline Box block_box(Box b, uint32_t (*red)[BLOCK / 64]) {
+__device__ inline Box block_box(Box b, uint32_t (*red)[PUSH_BLOCK / 64]) {
     b.lo = wave_box<false>(b.lo);
     b.hi = wave_box<true>(b.hi);
     const int w = threadIdx.x >> 6;
@@ -643,7 +648,7 @@ __device__ inline Box block_box(Box b, uint32_t (*red)[BLOCK / 64]) {
     __syncthreads();
     b.lo = red[0][0];
     b.hi = red[1][0];
-    for (int q = 1; q < BLOCK / 64; ++q) {
+    for (int q = 1; q < PUSH_BLOCK / 64; ++q) {
         b.lo = pk_min16(b.lo, red[0][q]);
         b.hi = pk_max16(b.hi, red[1][q]);
     }
@@ -675,7 +680,7 @@ __device__ inline bool state_cell(const GrainParams& gp, const PlainState& q, in
 }
 
 // Window from the chunk's bounding box (each lane's part in b).
-__device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*red)[BLOCK / 64]) {
+__device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*red)[PUSH_BLOCK / 64]) {
     b = block_box(b, red);
     const int i1a = cell_i1((int32_t)b.lo), i1b = cell_i1((int32_t)b.hi);
     const int i2a = cell_i2((int32_t)b.lo), i2b = cell_i2((int32_t)b.hi);
@@ -703,7 +708,7 @@ __device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*re
 }
 
 template <typename S, int PB>
-__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], uint32_t (*red)[BLOCK / 64]) {
+__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], uint32_t (*red)[PUSH_BLOCK / 64]) {
     Box b;
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
@@ -739,7 +744,7 @@ __device__ inline void deposit_one(const GrainParams& gp, const Window& w, doubl
 __device__ inline void flush_window(const GrainParams& gp, const Window& w, double* __restrict__ win,
                                     double* __restrict__ dep) {
     const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
-    for (int q = threadIdx.x; q < nodes_w; q += BLOCK) {
+    for (int q = threadIdx.x; q < nodes_w; q += PUSH_BLOCK) {
         double val = 0.0;
         for (int c = 0; c < C; ++c) {
             const int a = q * C + ((c + q) & (C - 1));
@@ -759,9 +764,9 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w, doub
 // cell) instead of four float ones, and the window sums do not depend on the
 // order of the additions.  With C copies a copy receives at most CHUNK / C
 // particles, each adding at most 1: the fraction bits 31 - log2(CHUNK / C)
-// keep every 32-bit sum below 2^31 (2^-20 .. 2^-24 for CHUNK = 2048).
+// keep every 32-bit sum below 2^31 (2^-19 .. 2^-23 for CHUNK = 4096).
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
-constexpr int SPLIT_CHUNK_LOG2 = ilog2(PushTraits<true>::PB * BLOCK);
+constexpr int SPLIT_CHUNK_LOG2 = ilog2(PushTraits<true>::PB * PUSH_BLOCK);
 __device__ inline int fx_bits(int C) { return 31 - SPLIT_CHUNK_LOG2 + (31 - __clz(C)); }
 
 __device__ inline void deposit_one(const GrainParams& gp, const Window& w,
@@ -794,7 +799,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
                                     unsigned long long* __restrict__ win, float* __restrict__ dep) {
     const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
     const double isc = 1.0 / (double)(1 << fx_bits(C));
-    for (int q = threadIdx.x; q < nodes_w; q += BLOCK) {
+    for (int q = threadIdx.x; q < nodes_w; q += PUSH_BLOCK) {
         const int row = q / w.W, col = q - row * w.W;
         unsigned long long sum = 0;
         for (int c = 0; c < C; ++c) sum += win[q * C + ((c + q) & (C - 1))] & 0xFFFFFFFFull;
@@ -803,7 +808,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
         if (sum) gadd(&dep[(w.wj0 + row) * nx + w.wi0 + col], (float)((double)sum * isc));
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nodes_w * C; q += BLOCK) win[q] = 0ull;
+    for (int q = threadIdx.x; q < nodes_w * C; q += PUSH_BLOCK) win[q] = 0ull;
 }
 
 __device__ inline SplitState load_state(const PBuf& b, int64_t p, SplitState*) { return load_split(b, p); }
@@ -950,7 +955,7 @@ __device__ inline void box_key(const GrainParams& gp, const PlainKey& k, Box& b)
 }
 
 template <typename K, int PB>
-__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], uint32_t (*red)[BLOCK / 64]) {
+__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], uint32_t (*red)[PUSH_BLOCK / 64]) {
     Box b;
 #pragma unroll
     for (int k = 0; k < PB; ++k) box_key(gp, key[k], b);
@@ -970,10 +975,10 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
     using A = typename Tr::A;
     using Key = typename KeyOf<SPLIT>::K;
     constexpr int PB = Tr::PB;
-    constexpr int CHUNK = PB * BLOCK;
+    constexpr int CHUNK = PB * PUSH_BLOCK;
     __shared__ A win[WIN_CAP];
-    __shared__ uint32_t red[2][BLOCK / 64];
-    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
+    __shared__ uint32_t red[2][PUSH_BLOCK / 64];
+    for (int q = threadIdx.x; q < WIN_CAP; q += PUSH_BLOCK) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
     int stride;
@@ -992,7 +997,7 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
         const int64_t base = (c - v.first_chunk) * CHUNK + threadIdx.x;
         Key key[PB];
 #pragma unroll
-        for (int k = 0; k < PB; ++k) load_key(v.b, base + k * BLOCK, v.n, key[k]);
+        for (int k = 0; k < PB; ++k) load_key(v.b, base + k * PUSH_BLOCK, v.n, key[k]);
         // the first particle's state loads while the window is reduced
         S buf[2];
         load_fields(v.b, base, v.n, buf[0]);
@@ -1021,15 +1026,15 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
         // buffer is copied (a copy would wait for the loads it moves)
 #pragma unroll 1
         for (int k = 0; k < PB; k += 2) {
-            const int64_t p = base + k * BLOCK;
-            load_fields(v.b, p + BLOCK, v.n, buf[1]);
+            const int64_t p = base + k * PUSH_BLOCK;
+            load_fields(v.b, p + PUSH_BLOCK, v.n, buf[1]);
             load_gather(v.grad, v.gp.nx, key[1], buf[1]);
             advance(p, buf[0], key[0]);
             if (k + 2 < PB) {
-                load_fields(v.b, p + 2 * BLOCK, v.n, buf[0]);
+                load_fields(v.b, p + 2 * PUSH_BLOCK, v.n, buf[0]);
                 load_gather(v.grad, v.gp.nx, key[2], buf[0]);
             }
-            advance(p + BLOCK, buf[1], key[1]);
+            advance(p + PUSH_BLOCK, buf[1], key[1]);
 #pragma unroll
             for (int a = 0; a + 2 < PB; ++a) key[a] = key[a + 2];
         }
@@ -1045,12 +1050,12 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
 
 // FP32: capped at 128 registers so four waves per SIMD stay resident (the
 // kernel is bound by memory latency); FP64 keeps its registers.
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(PUSH_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_push_split(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
     push_chunks<true>(tasks, prefix, ntasks, deposit);
 }
 
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(PUSH_BLOCK)
 k_push_plain(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
     push_chunks<false>(tasks, prefix, ntasks, deposit);
 }
@@ -1071,17 +1076,17 @@ __device__ inline void state_offsets(const GrainParams& gp, const PlainState& q,
 }
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(PUSH_BLOCK)
 k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks) {
     using Tr = PushTraits<SPLIT>;
     using S = typename Tr::S;
     using T = typename Tr::T;
     using A = typename Tr::A;
     constexpr int PB = Tr::PB;
-    constexpr int CHUNK = PB * BLOCK;
+    constexpr int CHUNK = PB * PUSH_BLOCK;
     __shared__ A win[WIN_CAP];
-    __shared__ uint32_t red[2][BLOCK / 64];
-    for (int q = threadIdx.x; q < WIN_CAP; q += BLOCK) win[q] = A(0);
+    __shared__ uint32_t red[2][PUSH_BLOCK / 64];
+    for (int q = threadIdx.x; q < WIN_CAP; q += PUSH_BLOCK) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
     int stride;
@@ -1098,7 +1103,7 @@ k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix
         S st[PB];
 #pragma unroll
         for (int k = 0; k < PB; ++k) {
-            const int64_t p = base + k * BLOCK + threadIdx.x;
+            const int64_t p = base + k * PUSH_BLOCK + threadIdx.x;
             if (p < n) st[k] = load_state(b, p, (S*)nullptr);
             else set_dead(st[k]);
         }
@@ -1830,7 +1835,7 @@ static bool is_split(apic_ctx* ctx) { return ctx->opts.precision == APIC_FP32_SP
 template <typename K>
 static int persistent_grid(apic_ctx* ctx, K kernel) {
     int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, BLOCK, 0) != hipSuccess || resident < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, PUSH_BLOCK, 0) != hipSuccess || resident < 1)
         resident = 1;
     const int per_cu = std::min(ctx->sched.push_wg_per_cu, resident);
     int g = ctx->num_cus * per_cu;
@@ -1841,9 +1846,9 @@ static int persistent_grid(apic_ctx* ctx, K kernel) {
 int push_resident_per_cu(apic_ctx* ctx) {
     int resident = 0;
     if (ctx->opts.precision == APIC_FP32_SPLIT)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_split, BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_split, PUSH_BLOCK, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_plain, BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_plain, PUSH_BLOCK, 0);
     return resident < 1 ? 1 : resident;
 }
 
@@ -1852,10 +1857,10 @@ hipError_t launch_push(apic_ctx* ctx, bool deposit) {
     hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
                        (int64_t)push_chunk(split), ctx->chunk_prefix);
     if (split)
-        hipLaunchKernelGGL(k_push_split, dim3(persistent_grid(ctx, k_push_split)), dim3(BLOCK), 0, ctx->stream,
+        hipLaunchKernelGGL(k_push_split, dim3(persistent_grid(ctx, k_push_split)), dim3(PUSH_BLOCK), 0, ctx->stream,
                            ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_push_plain, dim3(persistent_grid(ctx, k_push_plain)), dim3(BLOCK), 0, ctx->stream,
+        hipLaunchKernelGGL(k_push_plain, dim3(persistent_grid(ctx, k_push_plain)), dim3(PUSH_BLOCK), 0, ctx->stream,
                            ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
     return hipGetLastError();
 }
@@ -1865,10 +1870,10 @@ hipError_t launch_deposit(apic_ctx* ctx) {
     hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
                        (int64_t)push_chunk(split), ctx->chunk_prefix);
     if (split)
-        hipLaunchKernelGGL(k_deposit<true>, dim3(persistent_grid(ctx, k_deposit<true>)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_deposit<true>, dim3(persistent_grid(ctx, k_deposit<true>)), dim3(PUSH_BLOCK), 0,
                            ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     else
-        hipLaunchKernelGGL(k_deposit<false>, dim3(persistent_grid(ctx, k_deposit<false>)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_deposit<false>, dim3(persistent_grid(ctx, k_deposit<false>)), dim3(PUSH_BLOCK), 0,
                            ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     return hipGetLastError();
 }
