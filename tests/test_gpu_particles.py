@@ -13,9 +13,9 @@ pytestmark = pytest.mark.gpu
 FP64, FP32 = apic.APIC_FP64, apic.APIC_FP32_SPLIT
 
 
-def _frozen_pair(w, precision, n, seed, electrons=True, ions=True):
+def _frozen_pair(w, precision, n, seed, electrons=True, ions=True, capacity=0):
     ctx, sim = make_pair(w, precision, inject=False, frozen=True, electrons=electrons, ions=ions,
-                         n_macro=n)
+                         n_macro=n, capacity=capacity)
     rho = smooth_density(w["n1"], w["n2"], seed=seed, amplitude=1.5)
     apic.apic_solve_poisson(ctx, 0, rho, shape=shape_of(w))
     from oracle.poisson import source_from_density
@@ -143,6 +143,46 @@ def test_fp32_split_frozen_field_push_matches_oracle(alpha, wce):
             assert np.quantile(err, 0.99) <= 10 * np.quantile(base, 0.99) + 1e-6
             if s == 1:
                 assert np.quantile(err, 0.999) < 1e-5
+    finally:
+        apic.apic_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 8192, 12289])
+def test_chunk_boundaries_frozen_step(precision, n):
+    """Electron counts at and around the push's chunk boundaries (chunks of 4096
+    FP32 / 2048 FP64 particles: 512-thread workgroups with 8 / 4 particles each),
+    from a single particle to three chunks and one, beside a ragged ion
+    population: after one frozen-field step every particle matches the
+    oracle's and the bookkeeping is exact."""
+    w = scaled("c1", n1=48, n2=40)
+    w.update(alpha=0.2, wce=1.0, mi=25.0)
+    counts = (n, 2049)
+    ctx, sim = _frozen_pair(w, precision, 0, seed=3, capacity=max(counts) + 16)
+    try:
+        for s, vs in ((0, 1.0), (1, 0.2)):
+            parts = random_particles(counts[s], w["x1_out"], seed=31 + s, v_sigma=vs)
+            apic.apic_inject(ctx, 0, s, *parts)
+            sim.set_particles(s, *parts)
+        apic.apic_step(ctx, 1)
+        sim.run(1)
+        t = apic.apic_tallies(ctx, 0, 2, w["n2"])
+        for s, vs in ((0, 1.0), (1, 0.2)):
+            dev = apic.apic_particles(ctx, 0, s, counts[s])
+            ora = sim.particles(s)
+            err, common = particle_error(dev, ora, sim.grid, vs)
+            mismatch = len(dev["id"]) + len(ora["id"]) - 2 * common
+            print(f"precision={precision} n={n} s={s}: live {len(ora['id'])} mismatch {mismatch} "
+                  f"max {err.max() if len(err) else 0.0:.2e}", flush=True)
+            assert int(t["injected"][s]) == counts[s]
+            assert int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
+            assert int(t["resident"][s]) == len(dev["id"])
+            if precision == FP64:
+                assert mismatch == 0 and np.array_equal(dev["id"], ora["id"])
+                assert len(err) == 0 or err.max() < 1e-12
+            else:
+                assert mismatch <= 1
+                assert len(err) == 0 or (np.quantile(err, 0.999) < 2e-6 and err.max() < 1e-4)
     finally:
         apic.apic_free(ctx)
 
