@@ -36,15 +36,25 @@ COPY_BYTES = 1 << 30           # calibration copy: 1 GiB read + 1 GiB written
 
 
 def copy_calibration():
-    """A plain device copy of known size, run once outside the timed region so
-    that a hardware-counter run of this script can scale its byte counters."""
+    """A plain device copy of known size, outside the timed region: its first
+    run lets a hardware-counter run of this script scale its byte counters;
+    five more, timed with events, give the read-plus-write rate this GPU
+    sustains for a plain stream (GB/s of bytes read and written)."""
     import torch
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     y.copy_(x)
     torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    gbs = 5 * 2 * COPY_BYTES / (a.elapsed_time(b) * 1e-3) / 1e9
     del x, y
+    return gbs
 
 
 def measured_traffic(particles_per_launch, workload):
@@ -209,7 +219,7 @@ def main():
     from synthetic_inputs import WORKLOADS, ensemble_c4
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    copy_calibration()
+    copy_gbs = copy_calibration()
 
     # headline: the c4 ensemble, FP32 split, autotuned (the tuner's steps are
     # part of the warm-up)
@@ -243,7 +253,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_launch, "c4"),
                      "kernel": "k_push_split (FP32 split push+gather+deposit, all grains and species in one launch)",
                      "avg_launch_ms": push_avg_ms, "algorithmic_bytes_per_particle": BYTES_PER_PARTICLE["fp32"],
-                     "particles_per_launch": per_launch},
+                     "particles_per_launch": per_launch,
+                     # a plain 1 GiB device copy on the same GPU, read plus written bytes per second
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "breakdown_ms_per_step": breakdown(r32),
         "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1),
         "schedule": r32["schedule"],
