@@ -770,6 +770,62 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
     gbl(C.f)[idx] = 0.25 * acc;
 }
 
+
+// The same restriction from the finest level, by tiles of RT x RT coarse
+// nodes: the workgroup first forms the fine residuals under its tile once
+// each ((2 RT + 1)^2 nodes, into LDS), then every coarse node adds up its nine
+// weighted ones in the order above (the same sums, bit for bit).  The per-node
+// form evaluates the finest operator at every fine node for each of the up to
+// four coarse nodes that use it.
+constexpr int RT = 16;
+constexpr int RF = 2 * RT + 1;
+static_assert(RT * RT == MG_BLOCK, "one coarse node per thread");
+
+__global__ void __launch_bounds__(MG_BLOCK)
+k_restrict_residual_fine(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ coarse,
+                         const MGState* __restrict__ ms) {
+    __shared__ double res[RF * RF];
+    const MGDesc& F = fine[blockIdx.y];
+    const MGDesc& C = coarse[blockIdx.y];
+    if (C.n1 == 0 || !level_active(F, ms)) return;
+    const int n1c = C.n1, n2c = C.n2, nxc = n1c + 1;
+    const int n1f = F.n1, n2f = F.n2, nxf = n1f + 1;
+    const int tx = (nxc + RT - 1) / RT, ty = (n2c + RT) / RT;
+    if ((int)blockIdx.x >= tx * ty) return;
+    const int I0 = ((int)blockIdx.x % tx) * RT, J0 = ((int)blockIdx.x / tx) * RT;
+    const FineStencil st(F);
+    const gptr<const double> u = gbl(static_cast<const double*>(F.u));
+    const gptr<const double> f = gbl(static_cast<const double*>(F.f));
+    // fine node (2 J0 - 1 + b, 2 I0 - 1 + a) -> res[b RF + a]; 0 outside the unknowns
+    for (int t = threadIdx.x; t < RF * RF; t += MG_BLOCK) {
+        const int b = t / RF, a = t - b * RF;
+        const int i = 2 * I0 - 1 + a, j = 2 * J0 - 1 + b;
+        double r = 0.0;
+        if (i >= 1 && i <= n1f - 1 && j >= 0 && j <= n2f) r = f[(size_t)j * nxf + i] - apply_A(st, u, n2f, nxf, j, i);
+        res[t] = r;
+    }
+    __syncthreads();
+    const int I = I0 + (int)threadIdx.x % RT, J = J0 + (int)threadIdx.x / RT;
+    if (I > n1c || J > n2c) return;
+    const int idx = J * nxc + I;
+    gbl(C.u)[idx] = 0.0;
+    if (I == 0 || I == n1c) {
+        gbl(C.f)[idx] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int j = 2 * J + dj;
+        if (j < 0 || j > n2f) continue;
+        const double wj = dj == 0 ? 1.0 : 0.5;
+        for (int di = -1; di <= 1; ++di) {
+            const double wi = di == 0 ? 1.0 : 0.5;
+            acc += wj * wi * res[(2 * (J - J0) + dj + 1) * RF + 2 * (I - I0) + di + 1];
+        }
+    }
+    gbl(C.f)[idx] = 0.25 * acc;
+}
+
 // The same restriction from a level whose u is zero (every level below the
 // finest in a sawtooth cycle: the restriction into it cleared it), where the
 // residual is f itself: C.f = R F.f, C.u = 0.
@@ -1345,6 +1401,18 @@ hipError_t mg_extrapolate(apic_ctx* ctx) {
     return hipGetLastError();
 }
 
+// workgroups of the finest level's tiled restriction: the most coarse tiles of any grain
+static int restrict_tiles(const apic_ctx* ctx) {
+    const int G = (int)ctx->grains.size();
+    int tiles = 1;
+    for (int g = 0; g < G; ++g) {
+        const MGDesc& c = ctx->mgdesc_h[(size_t)G + g];
+        if (c.n1 == 0) continue;
+        tiles = std::max(tiles, ((c.n1 + RT) / RT) * ((c.n2 + RT) / RT));
+    }
+    return tiles;
+}
+
 // One V-cycle (sawtooth: restriction of the current residual down to the
 // coarsest level, then correction and smoothing on the way up) of every grain
 // not yet done, then (check) the residual norm and the convergence check.
@@ -1358,8 +1426,8 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol, bool check) {
             hipLaunchKernelGGL(k_restrict_residual<StoredStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
         else if (l == 0)
-            hipLaunchKernelGGL(k_restrict_residual<FineStencil>, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
-                               dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
+            hipLaunchKernelGGL(k_restrict_residual_fine, dim3(restrict_tiles(ctx), G), dim3(MG_BLOCK), 0,
+                               ctx->stream, ctx->mgdesc, ctx->mgdesc + (size_t)G, ctx->mgs);
         else  // level l's u was cleared by the restriction into it
             hipLaunchKernelGGL(k_restrict_rhs, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G,
