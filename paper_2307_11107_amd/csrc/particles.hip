@@ -39,18 +39,16 @@
 namespace apic {
 
 constexpr int BLOCK = 256;
-// Workgroup of the persistent push and deposit kernels: eight waves, two
-// workgroups per compute unit at four waves per SIMD.  A chunk of PB * 512
-// particles shares one deposit window, so a particle pays half the window
-// flushes and chunk-start barriers of a 256-thread workgroup.
-constexpr int PUSH_BLOCK = 512;
+// Largest workgroup of the persistent push and deposit kernels (their sizes
+// are PushTraits<SPLIT>::NT).
+constexpr int PUSH_BLOCK_MAX = 512;
 constexpr double FP64_DEAD = 1.0;   // x1 of a dead FP64 slot (valid x1 < 0)
 
 __device__ inline void atomic_add_f64(double* p, double v) { gadd(p, v); }
 
 // Block-wide sum of a per-thread u32 followed by one atomic per block.
 __device__ inline void block_count_add(uint32_t v, unsigned long long* dst) {
-    __shared__ uint32_t red[(BLOCK > PUSH_BLOCK ? BLOCK : PUSH_BLOCK) / 64];
+    __shared__ uint32_t red[(BLOCK > PUSH_BLOCK_MAX ? BLOCK : PUSH_BLOCK_MAX) / 64];
     uint32_t w = v;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
@@ -533,7 +531,7 @@ __device__ inline int push_plain_one(const GrainParams& gp, const SpeciesParams&
 
 // ----------------------------------------------------------------- ensemble push
 // One persistent launch pushes every (grain, species) task of the context.  The
-// tasks' particle slots are cut into chunks of PB * PUSH_BLOCK consecutive
+// tasks' particle slots are cut into chunks of PB * NT consecutive
 // (tile-sorted) particles; k_plan_chunks lays the chunks of all tasks end to
 // end.  The chunk range is split into eight contiguous parts, one per XCD
 // (workgroup b runs on XCD b mod 8), so that the chunks of neighbouring tiles,
@@ -549,18 +547,27 @@ template <> struct PushTraits<true> {
     using T = float;
     using A = unsigned long long;   // two 32-bit fixed-point sums per LDS word
     static constexpr int PB = 8;    // particles per thread and chunk (even)
+    // eight waves, two workgroups per CU at four waves per SIMD: a chunk of
+    // 4096 particles shares one deposit window, so a particle pays half the
+    // window flushes and chunk-start barriers of a 256-thread workgroup
+    static constexpr int NT = 512;
 };
 template <> struct PushTraits<false> {
     using S = PlainState;
     using T = double;
     using A = double;
     static constexpr int PB = 4;
+    // 174 registers allow eight waves per CU whatever the workgroup size; two
+    // 256-thread workgroups per CU overlap each other's serial phases
+    static constexpr int NT = 256;
 };
 
 constexpr int WIN_CAP = 4096;
 constexpr int WIN_MARGIN = 4;
 
-int push_chunk(bool split) { return PUSH_BLOCK * (split ? PushTraits<true>::PB : PushTraits<false>::PB); }
+int push_chunk(bool split) {
+    return split ? PushTraits<true>::NT * PushTraits<true>::PB : PushTraits<false>::NT * PushTraits<false>::PB;
+}
 
 // chunks of every task, laid end to end: prefix[t] = first chunk of task t
 __global__ void __launch_bounds__(BLOCK)
@@ -637,7 +644,8 @@ __device__ inline uint32_t wave_box(uint32_t x) {
     return x;
 }
 
-__device__ inline Box block_box(Box b, uint32_t (*red)[PUSH_BLOCK / 64]) {
+template <int NT>
+__device__ inline Box block_box(Box b, uint32_t (*red)[NT / 64]) {
     b.lo = wave_box<false>(b.lo);
     b.hi = wave_box<true>(b.hi);
     const int w = threadIdx.x >> 6;
@@ -648,7 +656,7 @@ __device__ inline Box block_box(Box b, uint32_t (*red)[PUSH_BLOCK / 64]) {
     __syncthreads();
     b.lo = red[0][0];
     b.hi = red[1][0];
-    for (int q = 1; q < PUSH_BLOCK / 64; ++q) {
+    for (int q = 1; q < NT / 64; ++q) {
         b.lo = pk_min16(b.lo, red[0][q]);
         b.hi = pk_max16(b.hi, red[1][q]);
     }
@@ -680,8 +688,9 @@ __device__ inline bool state_cell(const GrainParams& gp, const PlainState& q, in
 }
 
 // Window from the chunk's bounding box (each lane's part in b).
-__device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*red)[PUSH_BLOCK / 64]) {
-    b = block_box(b, red);
+template <int NT>
+__device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*red)[NT / 64]) {
+    b = block_box<NT>(b, red);
     const int i1a = cell_i1((int32_t)b.lo), i1b = cell_i1((int32_t)b.hi);
     const int i2a = cell_i2((int32_t)b.lo), i2b = cell_i2((int32_t)b.hi);
     Window w;
@@ -707,15 +716,15 @@ __device__ inline Window window_from(const GrainParams& gp, Box b, uint32_t (*re
     return w;
 }
 
-template <typename S, int PB>
-__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], uint32_t (*red)[PUSH_BLOCK / 64]) {
+template <int NT, typename S, int PB>
+__device__ inline Window chunk_window(const GrainParams& gp, const S (&st)[PB], uint32_t (*red)[NT / 64]) {
     Box b;
 #pragma unroll
     for (int k = 0; k < PB; ++k) {
         int i1, i2;
         if (state_cell(gp, st[k], i1, i2)) box_add(b, pack_cell(i1, i2));
     }
-    return window_from(gp, b, red);
+    return window_from<NT>(gp, b, red);
 }
 
 // FP64 form: one double per node copy.
@@ -744,7 +753,7 @@ __device__ inline void deposit_one(const GrainParams& gp, const Window& w, doubl
 __device__ inline void flush_window(const GrainParams& gp, const Window& w, double* __restrict__ win,
                                     double* __restrict__ dep) {
     const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
-    for (int q = threadIdx.x; q < nodes_w; q += PUSH_BLOCK) {
+    for (int q = threadIdx.x; q < nodes_w; q += PushTraits<false>::NT) {
         double val = 0.0;
         for (int c = 0; c < C; ++c) {
             const int a = q * C + ((c + q) & (C - 1));
@@ -766,7 +775,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w, doub
 // particles, each adding at most 1: the fraction bits 31 - log2(CHUNK / C)
 // keep every 32-bit sum below 2^31 (2^-19 .. 2^-23 for CHUNK = 4096).
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
-constexpr int SPLIT_CHUNK_LOG2 = ilog2(PushTraits<true>::PB * PUSH_BLOCK);
+constexpr int SPLIT_CHUNK_LOG2 = ilog2(PushTraits<true>::PB * PushTraits<true>::NT);
 __device__ inline int fx_bits(int C) { return 31 - SPLIT_CHUNK_LOG2 + (31 - __clz(C)); }
 
 __device__ inline void deposit_one(const GrainParams& gp, const Window& w,
@@ -799,7 +808,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
                                     unsigned long long* __restrict__ win, float* __restrict__ dep) {
     const int nodes_w = w.W * w.H, C = w.C, nx = gp.nx;
     const double isc = 1.0 / (double)(1 << fx_bits(C));
-    for (int q = threadIdx.x; q < nodes_w; q += PUSH_BLOCK) {
+    for (int q = threadIdx.x; q < nodes_w; q += PushTraits<true>::NT) {
         const int row = q / w.W, col = q - row * w.W;
         unsigned long long sum = 0;
         for (int c = 0; c < C; ++c) sum += win[q * C + ((c + q) & (C - 1))] & 0xFFFFFFFFull;
@@ -808,7 +817,7 @@ __device__ inline void flush_window(const GrainParams& gp, const Window& w,
         if (sum) gadd(&dep[(w.wj0 + row) * nx + w.wi0 + col], (float)((double)sum * isc));
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nodes_w * C; q += PUSH_BLOCK) win[q] = 0ull;
+    for (int q = threadIdx.x; q < nodes_w * C; q += PushTraits<true>::NT) win[q] = 0ull;
 }
 
 __device__ inline SplitState load_state(const PBuf& b, int64_t p, SplitState*) { return load_split(b, p); }
@@ -954,12 +963,12 @@ __device__ inline void box_key(const GrainParams& gp, const PlainKey& k, Box& b)
     if (key_cell(gp, k, i1, i2)) box_add(b, pack_cell(i1, i2));
 }
 
-template <typename K, int PB>
-__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], uint32_t (*red)[PUSH_BLOCK / 64]) {
+template <int NT, typename K, int PB>
+__device__ inline Window keys_window(const GrainParams& gp, const K (&key)[PB], uint32_t (*red)[NT / 64]) {
     Box b;
 #pragma unroll
     for (int k = 0; k < PB; ++k) box_key(gp, key[k], b);
-    return window_from(gp, b, red);
+    return window_from<NT>(gp, b, red);
 }
 
 template <bool SPLIT> struct KeyOf;
@@ -975,10 +984,11 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
     using A = typename Tr::A;
     using Key = typename KeyOf<SPLIT>::K;
     constexpr int PB = Tr::PB;
-    constexpr int CHUNK = PB * PUSH_BLOCK;
+    constexpr int NT = Tr::NT;
+    constexpr int CHUNK = PB * NT;
     __shared__ A win[WIN_CAP];
-    __shared__ uint32_t red[2][PUSH_BLOCK / 64];
-    for (int q = threadIdx.x; q < WIN_CAP; q += PUSH_BLOCK) win[q] = A(0);
+    __shared__ uint32_t red[2][NT / 64];
+    for (int q = threadIdx.x; q < WIN_CAP; q += NT) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
     int stride;
@@ -997,14 +1007,14 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
         const int64_t base = (c - v.first_chunk) * CHUNK + threadIdx.x;
         Key key[PB];
 #pragma unroll
-        for (int k = 0; k < PB; ++k) load_key(v.b, base + k * PUSH_BLOCK, v.n, key[k]);
+        for (int k = 0; k < PB; ++k) load_key(v.b, base + k * NT, v.n, key[k]);
         // the first particle's state loads while the window is reduced
         S buf[2];
         load_fields(v.b, base, v.n, buf[0]);
         load_gather(v.grad, v.gp.nx, key[0], buf[0]);
         Window w;
         w.on = false;
-        if (v.dep) w = keys_window(v.gp, key, red);
+        if (v.dep) w = keys_window<NT>(v.gp, key, red);
         auto advance = [&](int64_t p, S cur, const Key& kk) {
             set_key(cur, kk);
             int ia, ic;
@@ -1026,15 +1036,15 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
         // buffer is copied (a copy would wait for the loads it moves)
 #pragma unroll 1
         for (int k = 0; k < PB; k += 2) {
-            const int64_t p = base + k * PUSH_BLOCK;
-            load_fields(v.b, p + PUSH_BLOCK, v.n, buf[1]);
+            const int64_t p = base + k * NT;
+            load_fields(v.b, p + NT, v.n, buf[1]);
             load_gather(v.grad, v.gp.nx, key[1], buf[1]);
             advance(p, buf[0], key[0]);
             if (k + 2 < PB) {
-                load_fields(v.b, p + 2 * PUSH_BLOCK, v.n, buf[0]);
+                load_fields(v.b, p + 2 * NT, v.n, buf[0]);
                 load_gather(v.grad, v.gp.nx, key[2], buf[0]);
             }
-            advance(p + PUSH_BLOCK, buf[1], key[1]);
+            advance(p + NT, buf[1], key[1]);
 #pragma unroll
             for (int a = 0; a + 2 < PB; ++a) key[a] = key[a + 2];
         }
@@ -1050,12 +1060,12 @@ __device__ __forceinline__ void push_chunks(const PushTask* __restrict__ tasks, 
 
 // FP32: capped at 128 registers so four waves per SIMD stay resident (the
 // kernel is bound by memory latency); FP64 keeps its registers.
-__global__ void __launch_bounds__(PUSH_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(PushTraits<true>::NT) __attribute__((amdgpu_waves_per_eu(4)))
 k_push_split(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
     push_chunks<true>(tasks, prefix, ntasks, deposit);
 }
 
-__global__ void __launch_bounds__(PUSH_BLOCK)
+__global__ void __launch_bounds__(PushTraits<false>::NT)
 k_push_plain(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks, int deposit) {
     push_chunks<false>(tasks, prefix, ntasks, deposit);
 }
@@ -1076,17 +1086,18 @@ __device__ inline void state_offsets(const GrainParams& gp, const PlainState& q,
 }
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(PUSH_BLOCK)
+__global__ void __launch_bounds__(PushTraits<SPLIT>::NT)
 k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix, int ntasks) {
     using Tr = PushTraits<SPLIT>;
     using S = typename Tr::S;
     using T = typename Tr::T;
     using A = typename Tr::A;
     constexpr int PB = Tr::PB;
-    constexpr int CHUNK = PB * PUSH_BLOCK;
+    constexpr int NT = Tr::NT;
+    constexpr int CHUNK = PB * NT;
     __shared__ A win[WIN_CAP];
-    __shared__ uint32_t red[2][PUSH_BLOCK / 64];
-    for (int q = threadIdx.x; q < WIN_CAP; q += PUSH_BLOCK) win[q] = A(0);
+    __shared__ uint32_t red[2][NT / 64];
+    for (int q = threadIdx.x; q < WIN_CAP; q += NT) win[q] = A(0);
     __syncthreads();
     int64_t c, hi;
     int stride;
@@ -1103,11 +1114,11 @@ k_deposit(const PushTask* __restrict__ tasks, const int64_t* __restrict__ prefix
         S st[PB];
 #pragma unroll
         for (int k = 0; k < PB; ++k) {
-            const int64_t p = base + k * PUSH_BLOCK + threadIdx.x;
+            const int64_t p = base + k * NT + threadIdx.x;
             if (p < n) st[k] = load_state(b, p, (S*)nullptr);
             else set_dead(st[k]);
         }
-        const Window w = chunk_window(gp, st, red);
+        const Window w = chunk_window<NT>(gp, st, red);
         if (!w.on) continue;
 #pragma unroll
         for (int k = 0; k < PB; ++k) {
@@ -1833,9 +1844,9 @@ static bool is_split(apic_ctx* ctx) { return ctx->opts.precision == APIC_FP32_SP
 // what stays resident at once (a second round of workgroups would run alone
 // after the first and leave the chip underfilled), a multiple of 8 (XCDs).
 template <typename K>
-static int persistent_grid(apic_ctx* ctx, K kernel) {
+static int persistent_grid(apic_ctx* ctx, K kernel, int nt) {
     int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, PUSH_BLOCK, 0) != hipSuccess || resident < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, nt, 0) != hipSuccess || resident < 1)
         resident = 1;
     const int per_cu = std::min(ctx->sched.push_wg_per_cu, resident);
     int g = ctx->num_cus * per_cu;
@@ -1846,9 +1857,9 @@ static int persistent_grid(apic_ctx* ctx, K kernel) {
 int push_resident_per_cu(apic_ctx* ctx) {
     int resident = 0;
     if (ctx->opts.precision == APIC_FP32_SPLIT)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_split, PUSH_BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_split, PushTraits<true>::NT, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_plain, PUSH_BLOCK, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_push_plain, PushTraits<false>::NT, 0);
     return resident < 1 ? 1 : resident;
 }
 
@@ -1857,10 +1868,10 @@ hipError_t launch_push(apic_ctx* ctx, bool deposit) {
     hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
                        (int64_t)push_chunk(split), ctx->chunk_prefix);
     if (split)
-        hipLaunchKernelGGL(k_push_split, dim3(persistent_grid(ctx, k_push_split)), dim3(PUSH_BLOCK), 0, ctx->stream,
+        hipLaunchKernelGGL(k_push_split, dim3(persistent_grid(ctx, k_push_split, PushTraits<true>::NT)), dim3(PushTraits<true>::NT), 0, ctx->stream,
                            ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_push_plain, dim3(persistent_grid(ctx, k_push_plain)), dim3(PUSH_BLOCK), 0, ctx->stream,
+        hipLaunchKernelGGL(k_push_plain, dim3(persistent_grid(ctx, k_push_plain, PushTraits<false>::NT)), dim3(PushTraits<false>::NT), 0, ctx->stream,
                            ctx->tasks, ctx->chunk_prefix, ctx->ntasks, deposit ? 1 : 0);
     return hipGetLastError();
 }
@@ -1870,10 +1881,10 @@ hipError_t launch_deposit(apic_ctx* ctx) {
     hipLaunchKernelGGL(k_plan_chunks, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->tasks, ctx->ntasks,
                        (int64_t)push_chunk(split), ctx->chunk_prefix);
     if (split)
-        hipLaunchKernelGGL(k_deposit<true>, dim3(persistent_grid(ctx, k_deposit<true>)), dim3(PUSH_BLOCK), 0,
+        hipLaunchKernelGGL(k_deposit<true>, dim3(persistent_grid(ctx, k_deposit<true>, PushTraits<true>::NT)), dim3(PushTraits<true>::NT), 0,
                            ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     else
-        hipLaunchKernelGGL(k_deposit<false>, dim3(persistent_grid(ctx, k_deposit<false>)), dim3(PUSH_BLOCK), 0,
+        hipLaunchKernelGGL(k_deposit<false>, dim3(persistent_grid(ctx, k_deposit<false>, PushTraits<false>::NT)), dim3(PushTraits<false>::NT), 0,
                            ctx->stream, ctx->tasks, ctx->chunk_prefix, ctx->ntasks);
     return hipGetLastError();
 }
