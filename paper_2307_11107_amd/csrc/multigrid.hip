@@ -303,7 +303,9 @@ __device__ inline int xcd_line() {
 // value, only on its neighbour lines, so the first colour of the first sweep
 // after the correction reads its two neighbour rows prolonged (bilinear P) and
 // the other rows never need the correction added before they are solved.
-template <int K, int NT, class ST>
+// With TP > 0 each line is solved by the partition method (TP equations per
+// thread) instead of cyclic reduction over all of it.
+template <int K, int NT, class ST, int TP = 0>
 __global__ void __launch_bounds__(NT)
 k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int color,
            const MGDesc* __restrict__ cl) {
@@ -341,11 +343,12 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
         if (j > n2) return;
     }
     const int L = n1 - 1;
+    const int cap = TP > 0 && L < 2 * NT ? 2 * NT : L;
     double* a = lds;
-    double* b = a + L;
-    double* c = b + L;
-    double* d = c + L;
-    double* nb = d + L;     // rows j - 1 and j + 1 with the correction, [2][nx]
+    double* b = a + cap;
+    double* c = b + cap;
+    double* d = c + cap;
+    double* nb = d + cap;     // rows j - 1 and j + 1 with the correction, [2][nx]
     const int nx = n1 + 1;
     const ST st(D);
     const gptr<double> u = gbl(D.u);
@@ -397,8 +400,13 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
         d[k] = rhs;
     }
     __syncthreads();
-    pcr_solve<K, NT>(a, b, c, d, L, L);
-    for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * b[k];
+    if constexpr (TP > 0) {
+        tri_solve<TP, NT>(a, b, c, d, L);
+        for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k];
+    } else {
+        pcr_solve<K, NT>(a, b, c, d, L, L);
+        for (int k = threadIdx.x; k < L; k += NT) u[(size_t)j * nx + k + 1] = d[k] * b[k];
+    }
     }
 }
 
@@ -958,8 +966,10 @@ k_coarse_solve(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms) {
 }
 
 // ------------------------------------------------------------------ launches
-// Line-solve launches.  An x1 line gets 1024 threads beyond 512 unknowns, else
-// 256, an x2 line 512 beyond 256, else 256 (fewer equations per thread, a
+// Line-solve launches.  An x1 line of more than 1024 unknowns is solved by the
+// partition method (512 threads of five equations), one of 513 to 1024 by
+// cyclic reduction with 1024 threads, else 256; an x2 line gets 512 threads
+// beyond 256 unknowns, else 256 (fewer equations per thread, a
 // shorter PCR critical path).  Where a sweep has fewer than four lines per
 // compute unit, a line of 257 to 512 unknowns (x1) or more than 512 (x2) gets
 // one thread per unknown: with about one workgroup per compute unit the extra
@@ -979,6 +989,19 @@ static int pcr_k(int total, int nt) {
 // neighbour rows when it applies the coarse-grid correction
 static size_t x1_lds(int mn1, bool prolong) {
     return sizeof(double) * (4 * (size_t)(mn1 - 1) + (prolong ? 2 * (size_t)(mn1 + 1) : 0));
+}
+
+// x1 lines by the partition method (TP equations per thread, NT threads).
+template <int TP, int NT, class ST>
+static void relax_x1_tri(apic_ctx* ctx, int l, int color, bool prolong) {
+    const int mn1 = ctx->lvl_max_n1[l], mn2 = ctx->lvl_max_n2[l];
+    const size_t L = (size_t)std::max(mn1 - 1, 2 * NT);
+    const size_t lds = sizeof(double) * (4 * L + (prolong ? 2 * (size_t)(mn1 + 1) : 0));
+    const int lines = (mn2 + 1 - color + 1) / 2;
+    const int G = (int)ctx->grains.size();
+    hipLaunchKernelGGL((k_relax_x1<1, NT, ST, TP>), dim3(round8(lines), G), dim3(NT), lds, ctx->stream,
+                       ctx->mgdesc + (size_t)l * G, ctx->mgs, color,
+                       prolong ? ctx->mgdesc + (size_t)(l + 1) * G : (const MGDesc*)nullptr);
 }
 
 template <int K, int NT, class ST>
@@ -1041,7 +1064,12 @@ static void sweep_x1(apic_ctx* ctx, int l, bool prolong) {
     }
     for (int color = 0; color < colors; ++color) {
         const bool pro = prolong && color == 0;
-        if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<1024, ST>(ctx, l, color, pro);
+        // lines beyond 1024 unknowns (grids up to 2048 cells wide: at most 2047 <= 5 x 512):
+        // the partition method, whose chunk eliminations need no barrier and whose
+        // cyclic reduction runs on the 1024 chunk ends (c5 field 3.77 -> 3.42 ms against
+        // cyclic reduction over the whole line with 1024 threads)
+        if (ctx->lvl_max_n1[l] - 1 > 1024) relax_x1_tri<5, 512, ST>(ctx, l, color, pro);
+        else if (ctx->lvl_max_n1[l] - 1 > 512) relax_x1_k<1024, ST>(ctx, l, color, pro);
         else if (ctx->lvl_max_n1[l] - 1 > 256 && few_lines(ctx, ctx->lvl_lines_x1[l]))
             relax_x1_k<512, ST>(ctx, l, color, pro);
         else relax_x1_k<256, ST>(ctx, l, color, pro);

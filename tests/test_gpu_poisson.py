@@ -10,8 +10,11 @@ from synthetic_inputs import smooth_density
 
 pytestmark = pytest.mark.gpu
 
+# the last two have x1 lines of more than 1024 unknowns (solved by the partition
+# method on the finest level): c5's width, and a ragged one
 CASES = [(64, 64, 0.0, -0.1, 2.0), (64, 128, 0.15, -0.1, 1.0), (128, 64, -0.2, -0.3, 0.7),
-         (256, 256, 0.2, -0.1, 1.0), (512, 512, 0.2, -0.1, 1.0)]
+         (256, 256, 0.2, -0.1, 1.0), (512, 512, 0.2, -0.1, 1.0), (2048, 64, 0.2, -0.02, 5.0),
+         (1500, 40, 0.1, -0.05, 1.0)]
 
 
 def _ctx(n1, n2, alpha, xo, kappa, precision=apic.APIC_FP64):
