@@ -778,11 +778,10 @@ k_restrict_residual(const MGDesc* __restrict__ fine, const MGDesc* __restrict__ 
     gbl(C.f)[idx] = 0.25 * acc;
 }
 
-
 // The same restriction from the finest level, by tiles of RT x RT coarse
 // nodes: the workgroup first forms the fine residuals under its tile once
 // each ((2 RT + 1)^2 nodes, into LDS), then every coarse node adds up its nine
-// weighted ones in the order above (the same sums, bit for bit).  The per-node
+// weighted ones in the order above.  The per-node
 // form evaluates the finest operator at every fine node for each of the up to
 // four coarse nodes that use it.
 constexpr int RT = 16;
