@@ -1533,6 +1533,14 @@ __device__ inline void wave_runs(int key, int& head_lane, int& run_len, bool& is
     run_len = (gt ? (__ffsll((long long)gt) - 1) : 64) - lane;
 }
 
+// A value read from memory the kernel also writes (a vector load) that is the
+// same in every lane, moved to scalar registers: array bases selected by it are
+// then scalar too, and no loop waits on the vector load that produced them.
+__device__ inline int64_t uniform64(int64_t v) {
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v));
+}
+
 __device__ inline void sort_range(int64_t n, int blocks, int64_t& lo, int64_t& hi) {
     const int64_t per = (n + blocks - 1) / blocks;
     lo = min<int64_t>((int64_t)blockIdx.x * per, n);
@@ -1540,10 +1548,11 @@ __device__ inline void sort_range(int64_t n, int blocks, int64_t& lo, int64_t& h
 }
 
 // Batches of BLOCK slots per iteration of the histogram and scatter loops,
-// all their loads issued before the first is used, so a workgroup's slot range
-// streams with many loads in flight.
+// all their loads issued before the first is used (the scatter loads the next
+// batch while it ranks, stages and stores the current one), so a workgroup's
+// slot range streams with many loads in flight.
 constexpr int HIST_BATCHES = 8;
-constexpr int SCATTER_BATCHES = 4;
+constexpr int SCATTER_BATCHES = 3;
 static int scatter_batch() { return SCATTER_BATCHES * BLOCK; }
 
 template <bool SPLIT>
@@ -1557,9 +1566,9 @@ k_tile_hist(const PushTask* __restrict__ tasks, int max_level) {
     const int nt = gp.ntiles;
     for (int t = threadIdx.x; t < nt; t += BLOCK) lh[t] = 0;
     __syncthreads();
-    const PBuf b = T.buf[T.ctr->cur[T.s]];
+    const PBuf b = T.buf[__builtin_amdgcn_readfirstlane(T.ctr->cur[T.s])];
     int64_t lo, hi;
-    sort_range(T.ctr->n[T.s], SB, lo, hi);
+    sort_range(uniform64(T.ctr->n[T.s]), SB, lo, hi);
     for (int64_t base = lo; base < hi; base += HIST_BATCHES * BLOCK) {
         Moved<SPLIT> m[HIST_BATCHES];
         // every load is issued (a slot past the range reloads the last one):
@@ -1703,7 +1712,7 @@ template <> struct Words<false> {
 //     consecutive threads to consecutive slots, so the stores of a wave form
 //     whole cache lines instead of one partial line per particle.
 // LDS: cursors and counters per tile (2 x ntiles ints), the batch's tile list
-// (tile, count | first, destination), and the staged words.
+// (tile, count | first, destination), and the staged words and destinations.
 template <bool SPLIT>
 __global__ void __launch_bounds__(BLOCK)
 k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
@@ -1721,25 +1730,33 @@ k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
     int* keys = cnt + nt;             // [B] the batch's tiles, in order of first appearance
     int* first = keys + B;            // [B] their first position in tile order
     int* dest = first + B;            // [B] their first destination slot
-    uint32_t* stage = reinterpret_cast<uint32_t*>(dest + B);   // [NW][B]
+    uint32_t* stage = reinterpret_cast<uint32_t*>(dest + B);   // [NW + 1][B]
     for (int t = threadIdx.x; t < nt; t += BLOCK) {
         cur[t] = gbl(T.hist_off)[(size_t)t * SB + blockIdx.x];
         cnt[t] = 0;
     }
     if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
-    const int which = T.ctr->cur[T.s];
+    const int which = __builtin_amdgcn_readfirstlane(T.ctr->cur[T.s]);
     const PBuf src = T.buf[which];
     const PBuf dst = T.buf[1 - which];
     int64_t lo, hi;
-    sort_range(T.ctr->n[T.s], SB, lo, hi);
+    sort_range(uniform64(T.ctr->n[T.s]), SB, lo, hi);
+    if (lo >= hi) return;
+    // every load is issued (a slot past the range reloads the last one); the
+    // next batch is loaded while the current one is ranked, staged and stored
+    Moved<SPLIT> m[SCATTER_BATCHES];
+#pragma unroll
+    for (int k = 0; k < SCATTER_BATCHES; ++k) {
+        const int64_t p = lo + k * BLOCK + threadIdx.x;
+        load_moved(src, p < hi ? p : hi - 1, m[k]);
+    }
     for (int64_t base = lo; base < hi; base += B) {
-        Moved<SPLIT> m[SCATTER_BATCHES];
-        // every load is issued (a slot past the range reloads the last one)
+        Moved<SPLIT> nx[SCATTER_BATCHES];
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
-            const int64_t p = base + k * BLOCK + threadIdx.x;
-            load_moved(src, p < hi ? p : hi - 1, m[k]);
+            const int64_t p = base + B + k * BLOCK + threadIdx.x;
+            load_moved(src, p < hi ? p : hi - 1, nx[k]);
         }
         int key[SCATTER_BATCHES], rank[SCATTER_BATCHES];
 #pragma unroll
@@ -1781,13 +1798,15 @@ k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
             if (threadIdx.x == 0) nlive = run;
         }
         __syncthreads();
-        // stage in tile order
+        // stage in tile order, each particle with its destination slot
 #pragma unroll
         for (int k = 0; k < SCATTER_BATCHES; ++k) {
             if (key[k] < 0) continue;
-            const int pos = first[(cnt[key[k]] >> 16) - 1] + rank[k];
+            const int idx = (cnt[key[k]] >> 16) - 1;
+            const int pos = first[idx] + rank[k];
 #pragma unroll
             for (int w = 0; w < NW; ++w) stage[w * B + pos] = Words<SPLIT>::get(m[k], w);
+            stage[NW * B + pos] = (uint32_t)(dest[idx] + rank[k]);
         }
         __syncthreads();
         // consecutive threads write consecutive staged particles
@@ -1796,13 +1815,14 @@ k_tile_scatter(const PushTask* __restrict__ tasks, int max_level) {
             Moved<SPLIT> mm;
 #pragma unroll
             for (int w = 0; w < NW; ++w) Words<SPLIT>::set(mm, w, stage[w * B + q]);
-            const int idx = (cnt[tile_key(gp, mm)] >> 16) - 1;
-            store_moved(dst, (int64_t)dest[idx] + (q - first[idx]), mm);
+            store_moved(dst, (int64_t)stage[NW * B + q], mm);
         }
         __syncthreads();
         for (int i = threadIdx.x; i < nk; i += BLOCK) cnt[keys[i]] = 0;
         if (threadIdx.x == 0) nkeys = 0;
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SCATTER_BATCHES; ++k) m[k] = nx[k];
     }
 }
 
@@ -1903,7 +1923,7 @@ hipError_t launch_sort(apic_ctx* ctx, int first_task, int n_tasks, int max_level
     const size_t lds = sizeof(int) * (size_t)ctx->max_ntiles;
     // scatter: cursors and counters per tile, the batch's tile list and its staged words
     const size_t lds_scatter = sizeof(int) * (2 * (size_t)ctx->max_ntiles + 3 * (size_t)scatter_batch()) +
-                               sizeof(uint32_t) * (size_t)(split ? 7 : 11) * scatter_batch();
+                               sizeof(uint32_t) * (size_t)(split ? 8 : 12) * scatter_batch();
     const PushTask* t = ctx->tasks + first_task;
     const dim3 sgrid(ctx->max_sort_blocks, n_tasks);
     const dim3 cgrid(ctx->max_segs, n_tasks);
