@@ -188,6 +188,55 @@ def test_chunk_boundaries_frozen_step(precision, n):
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [3, 700, 9000, 200_000])
+def test_sort_block_count_does_not_change_particles(precision, n):
+    """The sort with one block per species and with 128 blocks (a large
+    capacity): for small n most of the 128 slot ranges are empty or hold a
+    partial batch, for large n one block streams hundreds of batches.  After
+    frozen-field steps that sort every step, both contexts hold the same
+    particles bit for bit, and they match the oracle."""
+    w = scaled("c1", n1=64, n2=48)
+    w.update(alpha=0.15, wce=0.6, mi=25.0)
+    counts = (n, 1000)
+    ctxs = []
+    try:
+        for cap in (max(counts) + 16, 4_200_000):
+            ctx, sim = make_pair(w, precision, inject=False, frozen=True, n_macro=0, capacity=cap, sort_every=1)
+            ctxs.append(ctx)
+            rho = smooth_density(w["n1"], w["n2"], seed=5, amplitude=1.5)
+            apic.apic_solve_poisson(ctx, 0, rho, shape=shape_of(w))
+            for s, vs in ((0, 1.0), (1, 0.2)):
+                apic.apic_inject(ctx, 0, s, *random_particles(counts[s], w["x1_out"], seed=41 + s, v_sigma=vs))
+            apic.apic_step(ctx, 5)
+        from oracle.poisson import source_from_density
+        sim.set_phi(sim.solver.solve(source_from_density(rho, w["kappa"]), -2.5, 0.0))
+        for s, vs in ((0, 1.0), (1, 0.2)):
+            sim.set_particles(s, *random_particles(counts[s], w["x1_out"], seed=41 + s, v_sigma=vs))
+        sim.run(5)
+        ta, tb = (apic.apic_tallies(c, 0, 2, w["n2"]) for c in ctxs)
+        for s, vs in ((0, 1.0), (1, 0.2)):
+            for k in ("injected", "absorbed", "escaped", "resident"):
+                assert int(ta[k][s]) == int(tb[k][s])
+            assert int(ta["injected"][s]) == int(ta["absorbed"][s] + ta["escaped"][s] + ta["resident"][s])
+            pa, pb = (apic.apic_particles(c, 0, s, counts[s]) for c in ctxs)
+            for k in ("id", "x1", "x2", "vR", "vZ", "vT"):
+                assert np.array_equal(pa[k], pb[k])
+            ora = sim.particles(s)
+            err, common = particle_error(pa, ora, sim.grid, vs)
+            mismatch = len(pa["id"]) + len(ora["id"]) - 2 * common
+            print(f"precision={precision} n={n} s={s}: live {len(pa['id'])} mismatch {mismatch} "
+                  f"max {err.max() if len(err) else 0.0:.2e}", flush=True)
+            if precision == FP64:
+                assert mismatch == 0 and (len(err) == 0 or err.max() < 1e-11)
+            else:
+                assert mismatch <= max(1, int(1e-4 * len(ora["id"])))
+                assert len(err) == 0 or np.quantile(err, 0.999) < 1e-5
+    finally:
+        for ctx in ctxs:
+            apic.apic_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
 def test_injection_matches_oracle(precision):
     """Injection from an empty domain in the vacuum field: counts are exact
     integers and the injected particles match by id after their partial step."""
