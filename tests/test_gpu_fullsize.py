@@ -1,4 +1,5 @@
-"""Full-size runs in the configuration the benchmark times: the c3 workload
+"""Full-size runs in the configuration the benchmark times: the c4 ensemble
+(64 grains in one context), the c3 workload
 (alpha = 0.2, omega_ce/omega_pe = 1, 512 x 512 cells, 5e7 macro-particles per
 species, injection, deposit, FP64 multigrid, sort), one full step through the
 C ABI.  The oracle cannot run 1e8 particles, so sampled particles are checked
@@ -16,7 +17,7 @@ import paper_2307_11107_amd as apic
 from gpu_util import particle_error
 from oracle.pic import Config, Simulation, Species
 from oracle.poisson import source_from_density
-from synthetic_inputs import WORKLOADS, smooth_density
+from synthetic_inputs import WORKLOADS, ensemble_c4, smooth_density
 
 pytestmark = pytest.mark.gpu
 
@@ -162,5 +163,107 @@ def test_c5_full_size_step_on_sampled_particles():
         rel = abs(q_dep - total) / (float(t["weight"][0]) * n)
         print(f"deposited charge {q_dep:.6e} expected {total:.6e} rel {rel:.2e}", flush=True)
         assert rel < 1e-5
+    finally:
+        apic.apic_free(ctx)
+
+
+def _manufactured(sim, x1_out, kappa):
+    """A potential with the Dirichlet values of the grain and the outer
+    boundary plus a smooth perturbation vanishing on both, and the charge
+    density the oracle's operator gives it: rho = -kappa^2 A phi_m."""
+    from oracle.poisson import assemble
+    X1, X2 = sim.grid.mesh()
+    s = (X1 + 1.0) / (x1_out + 1.0)
+    phi_m = -2.5 + 2.5 * s + 0.8 * np.sin(np.pi * s) * (1.0 + 0.5 * X2 + 0.3 * np.cos(2.0 * X2))
+    rho = -kappa ** 2 * (assemble(sim.grid) @ phi_m.ravel()).reshape(phi_m.shape)
+    rho[:, 0] = rho[:, -1] = 0.0
+    return phi_m, rho
+
+
+SAMPLE_C4 = 2_000
+
+
+def test_c4_full_size_ensemble_step():
+    """The c4 ensemble at full size, as the benchmark runs it: 64 grains of
+    128 x 128 ... 512 x 256 cells with 1e6 ... 2e7 macro-particles per species
+    (about 9e8 particles in all) in one context, FP32 split, injection, deposit,
+    multigrid.  Each grain's potential is manufactured (the oracle cannot
+    factorise 64 grids in a test's time): the GPU solve of its density must
+    return it (1e-10).  After one step every grain's bookkeeping is exact and
+    its deposited charge equals that of its resident particles; on every fourth
+    grain sampled load indices of both species move as the oracle moves them."""
+    grains = ensemble_c4()
+    G = len(grains)
+    checked = range(0, G, 4)
+    sims, rhos, phis, ids = [], [], [], {}
+    rng = np.random.default_rng(13)
+    for g, w in enumerate(grains):
+        n = w["n_macro"]
+        ocfg = Config(alpha=w["alpha"], n1=w["n1"], n2=w["n2"], x1_out=w["x1_out"], wce=w["wce"],
+                      kappa=w["kappa"], dt=w["dt"], seed=w["seed"], grain=g,
+                      species=[Species(q=-1.0, m=1.0, T=1.0, n=1.0, n_macro=n),
+                               Species(q=1.0, m=w["mi"], T=w["Ti"], n=1.0, n_macro=n)])
+        sim = Simulation(ocfg, vacuum_field=False)
+        sim.frozen = True
+        sim.inject_enabled = False
+        phi_m, rho = _manufactured(sim, w["x1_out"], w["kappa"])
+        sim.set_phi(phi_m)
+        if g in checked:
+            for s in range(2):
+                ids[g, s] = np.sort(rng.choice(n, min(SAMPLE_C4, n), replace=False))
+                sim.load(s, slots=ids[g, s])
+            sim.step()
+        sims.append(sim)
+        rhos.append(rho)
+        phis.append(phi_m)
+    print(f"c4 full size: {G} grains, {2 * sum(w['n_macro'] for w in grains):.3e} particles", flush=True)
+
+    cfgs = []
+    for w in grains:
+        sp = [apic.species(-1.0, 1.0, 1.0, 1.0, 0.0, 0.0, w["n_macro"]),
+              apic.species(1.0, w["mi"], w["Ti"], 1.0, 0.0, 0.0, w["n_macro"])]
+        cfgs.append(apic.grain_cfg(w["alpha"], w["n1"], w["n2"], sp, x1_out=w["x1_out"], wce=w["wce"],
+                                   kappa=w["kappa"], phi_grain=-2.5, phi_out=0.0, dt=w["dt"], seed=w["seed"]))
+    ctx = apic.apic_init(cfgs, apic.opts(precision=apic.APIC_FP32_SPLIT, inject=True))
+    try:
+        for g in range(G):
+            for s in range(2):
+                apic.apic_inject(ctx, g, s)
+        worst = 0.0
+        for g, w in enumerate(grains):
+            phi = apic.apic_solve_poisson(ctx, g, rhos[g], shape=(w["n2"] + 1, w["n1"] + 1))
+            worst = max(worst, float(np.max(np.abs(phi - phis[g])) / np.max(np.abs(phis[g]))))
+        print(f"manufactured potentials: worst rel err {worst:.2e}", flush=True)
+        assert worst < 1e-10
+        apic.apic_step(ctx, 1)
+        worst_q = 0.0
+        for g, w in enumerate(grains):
+            n = w["n_macro"]
+            sim = sims[g]
+            t = apic.apic_tallies(ctx, g, 2, w["n2"])
+            _, rho_dep = apic.apic_fields(ctx, g, (w["n2"] + 1, w["n1"] + 1))
+            total = 0.0
+            for s, vs in ((0, 1.0), (1, np.sqrt(w["Ti"] / w["mi"]))):
+                res = int(t["resident"][s])
+                assert int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
+                assert int(t["injected"][s]) == n + (sim.inj_inc[s] >> 32)
+                total += (-1.0 if s == 0 else 1.0) * float(t["weight"][s]) * res
+                if g in checked:
+                    dev = apic.apic_particles(ctx, g, s, res + 16)
+                    sub = sampled_rows(dev, ids[g, s])
+                    del dev
+                    ora = sim.particles(s)
+                    err, common = particle_error(sub, ora, sim.grid, vs)
+                    mismatch = len(sub["id"]) + len(ora["id"]) - 2 * common
+                    print(f"grain {g} ({w['n1']}x{w['n2']}, n={n}) s={s}: sampled {len(ora['id'])} "
+                          f"median {np.median(err):.2e} q99.9 {np.quantile(err, 0.999):.2e} max {err.max():.2e} "
+                          f"mismatch {mismatch}", flush=True)
+                    assert mismatch <= 2
+                    assert np.median(err) < 1e-6
+                    assert np.quantile(err, 0.999) < 1e-5
+            rel = abs(float(np.sum(rho_dep * sim.vol)) - total) / (float(t["weight"][0]) * n)
+            worst_q = max(worst_q, rel)
+        print(f"deposited charge: worst rel err {worst_q:.2e}", flush=True)
+        assert worst_q < 1e-5
     finally:
         apic.apic_free(ctx)
