@@ -51,6 +51,13 @@ def test_struct_layouts_match_header(tmp_path):
     assert got == want
 
 
+def _sp(**kw):
+    import paper_2307_11107_amd as apic
+    base = dict(q=-1, m=1, n_macro=10)
+    base.update(kw)
+    return apic.species(**base)
+
+
 def _cfg(**kw):
     import paper_2307_11107_amd as apic
     base = dict(alpha=0.1, n1=16, n2=16, species_list=[apic.species(-1, 1, n_macro=10)])
@@ -61,7 +68,15 @@ def _cfg(**kw):
 @pytest.mark.parametrize("kw,code", [(dict(alpha=0.25), _abi.APIC_ERANGE), (dict(alpha=-0.3), _abi.APIC_ERANGE),
                                      (dict(x1_out=0.0), _abi.APIC_ERANGE), (dict(x1_out=-1.0), _abi.APIC_ERANGE),
                                      (dict(n1=4), _abi.APIC_ERANGE), (dict(n2=4000), _abi.APIC_ERANGE),
-                                     (dict(dt=0.0), _abi.APIC_EINVAL), (dict(kappa=-1.0), _abi.APIC_EINVAL)])
+                                     (dict(dt=0.0), _abi.APIC_EINVAL), (dict(kappa=-1.0), _abi.APIC_EINVAL),
+                                     (dict(n1=2049), _abi.APIC_ERANGE), (dict(n2=2047), _abi.APIC_ERANGE),
+                                     (dict(n_bins=-1), _abi.APIC_EINVAL),
+                                     (dict(species_list=[]), _abi.APIC_EINVAL),
+                                     (dict(species_list=[_sp(n_macro=2_000_000_001)]), _abi.APIC_ERANGE),
+                                     (dict(species_list=[_sp(capacity=-1)]), _abi.APIC_EINVAL),
+                                     (dict(species_list=[_sp(weight=-1.0)]), _abi.APIC_EINVAL),
+                                     (dict(species_list=[_sp(T=-0.5)]), _abi.APIC_EINVAL),
+                                     (dict(species_list=[_sp(m=0.0)]), _abi.APIC_EINVAL)])
 def test_invalid_configurations_rejected_before_device_work(kw, code):
     import paper_2307_11107_amd as apic
     with pytest.raises(apic.ApicError) as e:

@@ -379,3 +379,19 @@ def test_call_order_and_invalid_particles_rejected():
         assert apic.apic_timing(ctx)["steps"] == 1
     finally:
         apic.apic_free(ctx)
+
+
+def test_capacity_limit_rejected():
+    """Particle slots are addressed with 32-bit byte offsets in the FP32 kernels:
+    a capacity of 2^30 or more, asked for or implied by n_macro (default
+    capacity 1.5 n_macro + margin), is refused with APIC_ERANGE at init, and
+    half the limit is accepted."""
+    def cfg(n_macro, capacity):
+        sp = [apic.species(-1.0, 1.0, n_macro=n_macro, capacity=capacity)]
+        return apic.grain_cfg(0.1, 16, 16, sp)
+    for n_macro, capacity in ((10, 1 << 30), (720_000_000, 0)):
+        with pytest.raises(apic.ApicError) as e:
+            apic.apic_init([cfg(n_macro, capacity)], apic.opts(precision=FP32))
+        assert e.value.code == apic.APIC_ERANGE
+    ctx = apic.apic_init([cfg(10, 1 << 29)], apic.opts(precision=FP32))
+    apic.apic_free(ctx)
