@@ -284,12 +284,16 @@ __device__ inline bool level_active(const MGDesc& D, const MGState* ms) {
     return D.n1 != 0 && !D.coarsest && !ms[blockIdx.y].done;
 }
 
-// line index of this workgroup: the lines are dealt out in eight contiguous
-// ranges, one per XCD (gridDim.x is a multiple of 8), so neighbouring lines,
-// which read each other's values, share an L2
-__device__ inline int xcd_line() {
-    const int per = gridDim.x >> 3;
-    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+// Index of this workgroup's line among the `lines` lines (or line blocks) of
+// its grain: they are dealt out in eight contiguous ranges, one per XCD
+// (blockIdx.x mod 8; gridDim.x is a multiple of 8 and at least the grain's
+// count rounded up to 8), so neighbouring lines, which read each other's
+// values, share an L2, and a grain with fewer lines than the largest one still
+// spreads them over all eight XCDs.  Workgroups left over get `lines` or more.
+__device__ inline int xcd_line(int lines) {
+    const int per = (lines + 7) >> 3;
+    const int k = (int)(blockIdx.x >> 3);
+    return k < per ? (int)(blockIdx.x & 7) * per + k : lines;
 }
 
 // Relaxation of the lines i2 = j (j = color, color + 2, ...): unknowns i1 = 1..n1-1.
@@ -316,7 +320,7 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     int j;
     int j_axis = -1;     // finest level (n2 >= 8), odd colour: the axis row solved after row j
     if constexpr (std::is_same<ST, FineStencil>::value) {
-        const int line = xcd_line();
+        const int line = xcd_line((n2 + 2 - color) / 2);
         j = color + 2 * line;
         if (color == 1 && j == 1) j_axis = 0;
         if (color == 1 && j == ((n2 & 1) ? n2 - 2 : n2 - 1)) j_axis = n2;
@@ -339,7 +343,7 @@ k_relax_x1(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
             return;
         }
     } else {
-        j = color + 2 * xcd_line();
+        j = color + 2 * xcd_line((n2 + 2 - color) / 2);
         if (j > n2) return;
     }
     const int L = n1 - 1;
@@ -423,7 +427,7 @@ k_relax_x2(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int co
     const MGDesc& D = lv[blockIdx.y];
     if (!level_active(D, ms)) return;
     const int n1 = D.n1, n2 = D.n2;
-    const int i0 = 1 + color + 2 * LPB * xcd_line();
+    const int i0 = 1 + color + 2 * LPB * xcd_line(((n1 - color) / 2 + LPB - 1) / LPB);
     if (i0 > n1 - 1) return;
     const int L = n2 + 1;
     const int total = LPB * L;
@@ -550,7 +554,7 @@ k_relax_x2t(const MGDesc* __restrict__ lv, const MGState* __restrict__ ms, int c
     const MGDesc& D = lv[blockIdx.y];
     if (!level_active(D, ms)) return;
     const int n1 = D.n1, n2 = D.n2;
-    const int i = 1 + color + 2 * xcd_line();
+    const int i = 1 + color + 2 * xcd_line((n1 - color) / 2);
     if (i > n1 - 1) return;
     const int L = n2 + 1;
     const int cap = L > 2 * NT ? L : 2 * NT;
