@@ -160,8 +160,9 @@ struct MGBatch {
 
 struct MGLevel {
     int n1, n2, nx, nodes;
-    double* st = nullptr;       // 9 stencil arrays [k * nodes + node], k = C,W,E,S,N,SW,SE,NW,NE
-                                // (coarse levels; the finest level's is evaluated at the nodes)
+    double* st = nullptr;       // the nine coefficients C,W,E,S,N,SW,SE,NW,NE node-major,
+                                // ST_STRIDE per node (stored levels; the default finest
+                                // level's operator is evaluated at the nodes)
     double* u = nullptr;        // solution (level 0: phi) / correction
     double* f = nullptr;        // right-hand side
     double* uT = nullptr;       // finest level: u, f transposed for the x2 sweeps
