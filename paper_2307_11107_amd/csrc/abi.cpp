@@ -408,6 +408,7 @@ void free_ctx(apic_ctx* ctx) {
     F(ctx->chunk_prefix);
     F(ctx->gdesc);
     F(ctx->mgdesc);
+    F(ctx->mgdesc_coarse);
     F(ctx->mgs);
     F(ctx->norm_part);
     F(ctx->mgb);
@@ -841,6 +842,16 @@ int build_tables(apic_ctx* ctx) {
     TRY(alloc_t(ctx, &ctx->mgdesc, ctx->mgdesc_h.size()));
     HIPCHK(ctx, hipMemcpy(ctx->mgdesc, ctx->mgdesc_h.data(), sizeof(MGDesc) * ctx->mgdesc_h.size(),
                           hipMemcpyHostToDevice));
+    // each grain's coarsest level, so that one launch solves every grain's dense system
+    std::vector<MGDesc> coarse_h(G);
+    ctx->max_coarse_m = 0;
+    for (int gi = 0; gi < G; ++gi) {
+        const int l = (int)ctx->grains[gi].mg.size() - 1;
+        coarse_h[gi] = ctx->mgdesc_h[(size_t)l * G + gi];
+        ctx->max_coarse_m = std::max(ctx->max_coarse_m, coarse_h[gi].m);
+    }
+    TRY(alloc_t(ctx, &ctx->mgdesc_coarse, (size_t)G));
+    HIPCHK(ctx, hipMemcpy(ctx->mgdesc_coarse, coarse_h.data(), sizeof(MGDesc) * G, hipMemcpyHostToDevice));
     TRY(alloc_t(ctx, &ctx->mgs, (size_t)G));
     TRY(alloc_t(ctx, &ctx->norm_part, (size_t)2 * G * ((ctx->lvl_max_nodes[0] + 255) / 256)));
     TRY(alloc_t(ctx, &ctx->mgb, 1));

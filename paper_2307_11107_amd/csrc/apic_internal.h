@@ -255,6 +255,8 @@ struct apic_ctx {
     int n_levels = 0;                       // deepest hierarchy of the ensemble
     std::vector<apic::MGDesc> mgdesc_h;     // [level][grain]
     apic::MGDesc* mgdesc = nullptr;
+    apic::MGDesc* mgdesc_coarse = nullptr;  // [grains] each grain's coarsest level
+    int max_coarse_m = 0;                   // largest dense system of the ensemble
     std::vector<int> lvl_max_n1, lvl_max_n2, lvl_max_nodes, lvl_lines_x1, lvl_lines_x2, lvl_max_m;
     apic::MGState* mgs = nullptr;           // [grains]
     double* norm_part = nullptr;            // [2][grains][blocks] partial norms (r, b)

@@ -1158,13 +1158,15 @@ static void smooth(apic_ctx* ctx, int l) {
     sweep_x1<FineStencil>(ctx, 0, false);
 }
 
-static void coarse_solve(apic_ctx* ctx, int l) {
+// The dense solves of every grain's coarsest level (whatever level that is) in
+// one launch.
+static void coarse_solve(apic_ctx* ctx) {
     const int G = (int)ctx->grains.size();
-    const int m = ctx->lvl_max_m[l];
+    const int m = ctx->max_coarse_m;
     if (m <= 0) return;
     const size_t lds = sizeof(double) * (size_t)((m + 1) & ~1);
     hipLaunchKernelGGL(k_coarse_solve, dim3((m + CS_ROWS - 1) / CS_ROWS, G), dim3(MG_BLOCK), lds, ctx->stream,
-                       ctx->mgdesc + (size_t)l * G, ctx->mgs);
+                       ctx->mgdesc_coarse, ctx->mgs);
 }
 
 static int norm_blocks(apic_ctx* ctx) { return (ctx->lvl_max_nodes[0] + MG_BLOCK - 1) / MG_BLOCK; }
@@ -1450,7 +1452,6 @@ static int restrict_tiles(const apic_ctx* ctx) {
 hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol, bool check) {
     const int G = (int)ctx->grains.size();
     const int nl = ctx->n_levels;
-    coarse_solve(ctx, 0);
     for (int l = 0; l + 1 < nl; ++l) {
         const int cn = ctx->lvl_max_nodes[l + 1];
         if (l == 0 && ctx->opts.conservative_poisson)
@@ -1463,8 +1464,8 @@ hipError_t mg_vcycle_launches(apic_ctx* ctx, double tol, bool check) {
             hipLaunchKernelGGL(k_restrict_rhs, dim3((cn + MG_BLOCK - 1) / MG_BLOCK, G),
                                dim3(MG_BLOCK), 0, ctx->stream, ctx->mgdesc + (size_t)l * G,
                                ctx->mgdesc + (size_t)(l + 1) * G, ctx->mgs);
-        coarse_solve(ctx, l + 1);
     }
+    coarse_solve(ctx);   // each grain's restriction chain ends at its coarsest level
     for (int l = nl - 2; l >= 0; --l) smooth(ctx, l);   // correction applied by the first sweep
     if (check) residual_check(ctx, tol, 1, false);
     return hipGetLastError();
