@@ -201,7 +201,7 @@ def _inside_brute(P, alpha):
 
 @pytest.mark.parametrize("alpha", [0.0, 0.1, 0.2, -0.2, 0.24, -0.2499])
 def test_chord_impact_matches_dense_sampling(alpha):
-    """Any |alpha| < 1/4: the chord test's verdict and first crossing against a
+    """Any |alpha| < 1/4: the chord test's outcome and first crossing against a
     brute-force scan of 8001 points per chord with the grain's definition
     r <= rho(x2) (cases within 1e-7 of grazing, where the scan itself is unsure,
     are left out)."""
