@@ -89,9 +89,14 @@ def grain_cfgs(grains, boltzmann=False):
     return cfgs
 
 
+TUNING_STEPS_MAX = 96
+
+
 def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=False, conservative=False):
-    """Loads every grain, runs `warmup` steps (the autotuner's steps among
-    them), then times `steps` steps between device synchronisations."""
+    """Loads every grain; with the autotuner, steps until the schedule is
+    chosen (untimed, whatever `warmup` is, so that no timed step runs a tuning
+    candidate); then runs `warmup` steps and times `steps` steps between device
+    synchronisations."""
     import torch
     import paper_2307_11107_amd as apic
     prec = apic.APIC_FP32_SPLIT if precision == "fp32" else apic.APIC_FP64
@@ -103,6 +108,10 @@ def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=
         for g in range(len(grains)):
             for s in range(ns):
                 apic.apic_inject(ctx, g, s)
+        tuning_steps = 0
+        while autotune and not apic.apic_schedule(ctx)["tuned"] and tuning_steps < TUNING_STEPS_MAX:
+            apic.apic_step(ctx, 1)
+            tuning_steps += 1
         apic.apic_step(ctx, warmup)
         torch.cuda.synchronize()
         t0 = [apic.apic_tallies(ctx, g, ns, w["n2"]) for g, w in enumerate(grains)]
@@ -121,7 +130,7 @@ def run_gpu(grains, precision, steps, warmup, stream, autotune=False, boltzmann=
     balance = all(int(t["injected"][s]) == int(t["absorbed"][s] + t["escaped"][s] + t["resident"][s])
                   for t in t1 for s in range(ns))
     return {"elapsed": elapsed, "particle_steps": pushed, "timing": tm, "balance_exact": balance,
-            "schedule": sched}
+            "schedule": sched, "tuning_steps": tuning_steps}
 
 
 def _cpu_grain(args):
@@ -259,6 +268,8 @@ def main():
         "breakdown_ms_per_step": breakdown(r32),
         "mg_cycles_per_step": tm["mg_cycles"] / max(tm["steps"], 1),
         "schedule": r32["schedule"],
+        # untimed steps the autotuner took to choose the schedule, before the warmup
+        "tuning_steps": r32["tuning_steps"],
         "balance_exact": r32["balance_exact"],
     }
     if not args.no_fp64:

@@ -1086,6 +1086,9 @@ int autotune(apic_ctx* ctx, int64_t* left) {
         }
         TRY(finish_step(ctx));
         --*left;
+        // the last phase left the particles 16 pushes out of order: the run
+        // continues from a fresh sort of every task
+        if (ctx->tuned) TRY(sort_all(ctx));
     }
     ctx->tuning = false;
     return APIC_OK;
